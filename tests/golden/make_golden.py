@@ -1,0 +1,61 @@
+"""Writes the stored expected values under tests/golden/ by running the FP64
+oracle (oracle/) on the seeded synthetic feeders (opfgen/).  Nothing here
+touches the HIP library.
+
+    python tests/golden/make_golden.py 13bus 123bus     # seconds
+    python tests/golden/make_golden.py 8500bus          # tens of minutes
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from opfgen import by_name, build_instance  # noqa: E402
+from oracle import admm  # noqa: E402
+
+RHO = 100.0
+
+
+def golden(name, seed=0, eps_rel=1e-4, n_sample=256):
+    f = by_name(name, seed)
+    inst = build_instance(f)
+    P = admm.setup(inst)
+    t0 = time.time()
+    r = admm.solve(P, rho=RHO, eps_rel=eps_rel, max_iter=2_000_000, record=True, progress=5000)
+    dt = time.time() - t0
+    vidx = np.nonzero(inst.var_kind == 2)[0]
+    rng = np.random.default_rng(12345)
+    samp = np.sort(rng.choice(vidx, size=min(n_sample, len(vidx)), replace=False))
+    hist = r.history
+    m = hist[:, 0] ** 2 + (hist[:, 1] / RHO) ** 2
+    out = dict(
+        workload=name, seed=seed, rho=RHO, eps_rel=eps_rel, stats=inst.stats(),
+        iterations=int(r.iterations), converged=bool(r.converged), objective=r.objective,
+        pres=r.pres, dres=r.dres, eps_prim=r.eps_prim, eps_dual=r.eps_dual,
+        w_index=[int(i) for i in samp], w_value=[float(r.x[i]) for i in samp],
+        w_min=float(r.x[vidx].min()), w_max=float(r.x[vidx].max()), w_sum=float(r.x[vidx].sum()),
+        x_sum=float(r.x.sum()),
+        history_every=max(1, r.iterations // 200),
+        merit_history=[float(v) for v in m[::max(1, r.iterations // 200)]],
+        oracle_seconds=dt,
+        source="oracle/admm.py solve() on opfgen.by_name(workload, seed); written by tests/golden/make_golden.py",
+    )
+    path = os.path.join(HERE, f"admm_{name}_s{seed}_eps{eps_rel:g}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"wrote {path}: {r.iterations} iterations, objective {r.objective:.12g}, {dt:.1f}s", flush=True)
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or ["13bus", "123bus"]
+    for nm in names:
+        eps = 1e-4
+        if ":" in nm:
+            nm, e = nm.split(":")
+            eps = float(e)
+        golden(nm, eps_rel=eps)
