@@ -1,0 +1,213 @@
+/*
+ * opf_admm.h -- C ABI of the MI355X (gfx950) solver-free componentwise ADMM
+ * for multi-phase linearised distribution OPF (Ryu, Byeon, Kim, "A
+ * GPU-Accelerated Distributed Algorithm for Optimal Power Flow in Distribution
+ * Systems").
+ *
+ * The library solves the reformulated model of Section III-A (OurModel):
+ *
+ *     min c^T x   s.t.  A_s x_s = b_s      for every component s,
+ *                       B_s x   = x_s      (consensus),
+ *                       lb <= x <= ub      (bounds kept out of the components)
+ *
+ * with Algorithm 1: a clipped consensus average (global update, closed_1 in
+ * its sparse form global_sparse), the closed-form projection of each
+ * component's local copy onto {A_s y = b_s} (local update, closed_2), the
+ * dual update (ADMM-3) and the relative primal/dual residual test
+ * (termination).  The per-component factors of closed_2 are precomputed once
+ * from the row-reduced A_s (Section IV-B).
+ *
+ * Conventions for every call:
+ *   - plain pointers and sizes only; no framework types;
+ *   - host pointers passed to opf_admm_setup are read during the call only
+ *     and never retained (the caller keeps ownership);
+ *   - device memory allocated by the library belongs to the handle and is
+ *     released by opf_admm_destroy;
+ *   - all device work of a handle runs on the HIP stream given at setup
+ *     (NULL = the null stream); every call returns with that work finished;
+ *   - calls on one handle are not thread-safe; distinct handles are
+ *     independent;
+ *   - return value: 0 on success, OPF_NOT_CONVERGED (a warning, +1) when
+ *     max_iter was reached, a negative OPF_E* code on error.  The message of
+ *     the last error is available from opf_admm_last_error.
+ */
+#ifndef OPF_ADMM_H
+#define OPF_ADMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define OPF_OK                     0
+#define OPF_NOT_CONVERGED          1   /* max_iter reached; outputs hold the last iterate */
+#define OPF_EINVAL                (-1) /* bad sizes, NaN/Inf in A, b or c, index out of range, duplicate index in one B_s */
+#define OPF_EBOUNDS               (-2) /* lb > ub or NaN bound */
+#define OPF_EUNCOVERED            (-3) /* a global variable has no local copy: B^T B singular (Section IV-C) */
+#define OPF_EINFEASIBLE_COMPONENT (-4) /* row reduction found 0 = nonzero in [A_s | b_s] (Section IV-B) */
+#define OPF_ENOMEM                (-5)
+#define OPF_EHIP                  (-6) /* a HIP runtime call failed */
+#define OPF_ENUMERIC              (-7) /* NaN/Inf appeared in the residuals */
+#define OPF_EHANG                 (-8) /* a bounded device-side wait ran out (persistent kernel) */
+
+/* ---- precision of the iteration ----------------------------------------- */
+#define OPF_PREC_FP64   0   /* factors, state, residuals all FP64 */
+#define OPF_PREC_MIXED  1   /* FP32 factors/state in the bulk phase, FP64 residual sums,
+                               then FP64 polish iterations until the FP64 test holds */
+
+/* ---- kernel schedule ----------------------------------------------------- */
+#define OPF_KERNEL_AUTO        0
+#define OPF_KERNEL_STEP        1  /* one fused launch per iteration, host checks a device flag */
+#define OPF_KERNEL_PERSISTENT  2  /* one cooperative launch runs all iterations */
+
+/*
+ * Problem data: the componentwise LP of OurModel.
+ *   n          number of global variables x
+ *   c[n]       objective (c^T x)
+ *   lb[n], ub[n]  bounds, +-INFINITY allowed, lb <= ub
+ *   var_kind[n]   0 = no bounds, 1 = bounded, 2 = voltage (squared magnitude).
+ *                 Used only by the default initial point of Section V-A:
+ *                 a local copy starts at 1 for a voltage, at the midpoint of
+ *                 [lb, ub] when both bounds are finite, otherwise at 0.
+ *   S          number of components
+ *   comp_m[S], comp_n[S]   rows and columns of each A_s (m_s >= 0, 1 <= n_s <= 64)
+ *   A_vals     concatenated row-major m_s x n_s blocks
+ *   b_vals     concatenated b_s (length m_s each)
+ *   idx        concatenated global indices of each component's columns
+ *              (the 0/1 matrix B_s of Section II-B: local slot j copies x[idx_j]);
+ *              no index repeats inside one component.
+ * The stacked local vector z = [x_1; ...; x_S] has L = sum n_s entries in
+ * this concatenated order ("user slot order").
+ */
+typedef struct opf_problem {
+    int32_t        n;
+    const double*  c;
+    const double*  lb;
+    const double*  ub;
+    const uint8_t* var_kind;
+    int32_t        S;
+    const int32_t* comp_m;
+    const int32_t* comp_n;
+    const double*  A_vals;
+    const double*  b_vals;
+    const int32_t* idx;
+} opf_problem;
+
+/*
+ * Options.  opf_admm_default_options fills the paper's defaults
+ * (rho = 100, eps_rel = 1e-3, Section V-A).
+ */
+typedef struct opf_admm_options {
+    double  rho;            /* ADMM penalty (> 0) */
+    double  eps_rel;        /* relative tolerance of the termination test (> 0) */
+    int64_t max_iter;       /* iteration cap (>= 1) */
+    int32_t precision;      /* OPF_PREC_FP64 or OPF_PREC_MIXED */
+    int32_t polish;         /* MIXED only: 1 = finish with FP64 iterations until the FP64 test holds */
+    int32_t check_every;    /* STEP schedule: iterations enqueued between host checks of the stop flag */
+    int32_t kernel;         /* OPF_KERNEL_* */
+    int32_t history_cap;    /* per-iteration residual history kept on the device (0 = none) */
+    int32_t block_waves;    /* wavefronts per workgroup (0 = autotuned) */
+    int32_t reserved[7];
+} opf_admm_options;
+
+/* Optional warm start: z0 and lambda0 in user slot order (length L). */
+typedef struct opf_warm {
+    const double* z;
+    const double* lam;
+    int32_t       on_device;   /* 1: device pointers, 0: host pointers */
+} opf_warm;
+
+/*
+ * Outputs of a solve.  x (length n) is required; z and lam (length L, user
+ * slot order) are optional (NULL = not written).  The pointers are caller
+ * owned, host or device as flagged.
+ */
+typedef struct opf_result {
+    double*  x;
+    double*  z;
+    double*  lam;
+    int32_t  outputs_on_device;
+    int32_t  status;           /* same as the return value of the solve */
+    int64_t  iterations;       /* completed iterations (all phases) */
+    int64_t  iterations_fp32;  /* MIXED: iterations of the FP32 bulk phase */
+    double   objective;        /* c^T x */
+    double   pres, dres, eps_prim, eps_dual;   /* termination quantities at the last iteration */
+    double   solve_ms;         /* wall time of the solve on the host clock */
+} opf_result;
+
+typedef struct opf_residuals {
+    int64_t iterations;
+    double  pres, dres, eps_prim, eps_dual;
+} opf_residuals;
+
+/* Layout and size information of a handle (for diagnostics and benchmarks). */
+typedef struct opf_admm_info {
+    int32_t n, S, L;           /* global variables, components, slots */
+    int32_t waves, lanes;      /* packed wavefronts and their lanes (64 each) */
+    int32_t max_ns, max_copies;
+    int64_t sum_ns2;           /* sum over components of n_s^2 */
+    int64_t factor_bytes_fp64; /* device bytes of the packed FP64 factors */
+    int64_t device_bytes;      /* all device memory owned by the handle */
+    double  setup_ms;          /* host factorisation + packing + upload */
+    int32_t grid_blocks;       /* persistent schedule: co-resident workgroups */
+    int32_t block_waves;
+} opf_admm_info;
+
+typedef struct opf_admm_handle opf_admm_handle;
+
+void opf_admm_default_options(opf_admm_options* o);
+
+/*
+ * Validates the problem, row-reduces each [A_s | b_s] (Section IV-B),
+ * precomputes F_s = I - A_s^T (A_s A_s^T)^{-1} A_s (= -Abar_s) and
+ * bbar_s = A_s^T (A_s A_s^T)^{-1} b_s in FP64 (closed_2 and Algorithm 1's
+ * precomputation), builds the copy lists of B^T (whose Gram matrix B^T B is
+ * diagonal, Section IV-C), packs components into 64-lane wavefronts and
+ * uploads everything to the device on `hip_stream` (a hipStream_t, NULL for
+ * the null stream).  On success *out receives a handle.  On error *out is
+ * NULL and the message is available from opf_admm_last_error(NULL).
+ */
+int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_stream,
+                   opf_admm_handle** out);
+
+/*
+ * Runs Algorithm 1 from the default initial point (Section V-A) or from
+ * `warm` (nullable) until the termination test holds or max_iter iterations
+ * have run.  Writes the outputs requested in r and its scalar fields.
+ * Returns OPF_OK, OPF_NOT_CONVERGED, OPF_ENUMERIC or another error.
+ */
+int opf_admm_solve(opf_admm_handle* h, const opf_warm* warm, opf_result* r);
+
+/*
+ * Runs exactly `iters` iterations (no termination test) from the default
+ * initial point or `warm`, with the handle's precision, and writes the
+ * outputs like opf_admm_solve.  Meant for trajectory comparisons at a fixed
+ * iteration count.
+ */
+int opf_admm_run_fixed(opf_admm_handle* h, const opf_warm* warm, int64_t iters, opf_result* r);
+
+/*
+ * Residuals of the current state and, when hist != NULL, the per-iteration
+ * history as rows (pres, dres, eps_prim, eps_dual): up to
+ * min(hist_cap, options.history_cap, iterations) rows are written.  Returns the
+ * number of rows written, or a negative error.
+ */
+int opf_admm_residuals(const opf_admm_handle* h, opf_residuals* out, double* hist, int hist_cap);
+
+/* Copies layout and size information of the handle. */
+int opf_admm_get_info(const opf_admm_handle* h, opf_admm_info* info);
+
+/* Frees the handle and its device memory.  NULL is ignored. */
+void opf_admm_destroy(opf_admm_handle* h);
+
+/* Message of the last error of h (or of the last failed setup when h is NULL).
+   Owned by the library; valid until the next call on the same handle. */
+const char* opf_admm_last_error(const opf_admm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OPF_ADMM_H */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) solver-free componentwise ADMM for multi-phase linearised
+distribution OPF.
+
+The compute path is the HIP library `libopf_admm.so` behind the C ABI of
+include/opf_admm.h; `binding` marshals arguments to it.  There is no CPU
+fallback: using the solver without the built library raises."""
+from . import binding
+from .binding import (OPF_KERNEL_AUTO, OPF_KERNEL_PERSISTENT, OPF_KERNEL_STEP, OPF_PREC_FP64,
+                      OPF_PREC_MIXED, OpfError, Solver)
+
+__all__ = ["binding", "Solver", "OpfError", "OPF_PREC_FP64", "OPF_PREC_MIXED", "OPF_KERNEL_AUTO",
+           "OPF_KERNEL_STEP", "OPF_KERNEL_PERSISTENT"]

@@ -1,0 +1,285 @@
+"""Python binding of the C ABI in include/opf_admm.h (argument marshalling only).
+
+Every step of the iteration runs in the HIP library `libopf_admm.so`; this
+module only converts arrays and structs.  Importing it fails loudly when the
+library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libopf_admm.so")
+
+OPF_OK = 0
+OPF_NOT_CONVERGED = 1
+OPF_EINVAL = -1
+OPF_EBOUNDS = -2
+OPF_EUNCOVERED = -3
+OPF_EINFEASIBLE_COMPONENT = -4
+OPF_ENOMEM = -5
+OPF_EHIP = -6
+OPF_ENUMERIC = -7
+OPF_EHANG = -8
+
+OPF_PREC_FP64 = 0
+OPF_PREC_MIXED = 1
+
+OPF_KERNEL_AUTO = 0
+OPF_KERNEL_STEP = 1
+OPF_KERNEL_PERSISTENT = 2
+
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBOUNDS", -3: "EUNCOVERED",
+                -4: "EINFEASIBLE_COMPONENT", -5: "ENOMEM", -6: "EHIP", -7: "ENUMERIC", -8: "EHANG"}
+
+EXPORTED = ["opf_admm_default_options", "opf_admm_setup", "opf_admm_solve", "opf_admm_run_fixed",
+            "opf_admm_residuals", "opf_admm_get_info", "opf_admm_destroy", "opf_admm_last_error"]
+
+
+class opf_problem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("c", C.POINTER(C.c_double)), ("lb", C.POINTER(C.c_double)),
+                ("ub", C.POINTER(C.c_double)), ("var_kind", C.POINTER(C.c_uint8)), ("S", C.c_int32),
+                ("comp_m", C.POINTER(C.c_int32)), ("comp_n", C.POINTER(C.c_int32)),
+                ("A_vals", C.POINTER(C.c_double)), ("b_vals", C.POINTER(C.c_double)),
+                ("idx", C.POINTER(C.c_int32))]
+
+
+class opf_admm_options(C.Structure):
+    _fields_ = [("rho", C.c_double), ("eps_rel", C.c_double), ("max_iter", C.c_int64),
+                ("precision", C.c_int32), ("polish", C.c_int32), ("check_every", C.c_int32),
+                ("kernel", C.c_int32), ("history_cap", C.c_int32), ("block_waves", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
+
+
+class opf_warm(C.Structure):
+    _fields_ = [("z", C.c_void_p), ("lam", C.c_void_p), ("on_device", C.c_int32)]
+
+
+class opf_result(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("z", C.c_void_p), ("lam", C.c_void_p), ("outputs_on_device", C.c_int32),
+                ("status", C.c_int32), ("iterations", C.c_int64), ("iterations_fp32", C.c_int64),
+                ("objective", C.c_double), ("pres", C.c_double), ("dres", C.c_double),
+                ("eps_prim", C.c_double), ("eps_dual", C.c_double), ("solve_ms", C.c_double)]
+
+
+class opf_residuals(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("pres", C.c_double), ("dres", C.c_double),
+                ("eps_prim", C.c_double), ("eps_dual", C.c_double)]
+
+
+class opf_admm_info(C.Structure):
+    _fields_ = [("n", C.c_int32), ("S", C.c_int32), ("L", C.c_int32), ("waves", C.c_int32),
+                ("lanes", C.c_int32), ("max_ns", C.c_int32), ("max_copies", C.c_int32),
+                ("sum_ns2", C.c_int64), ("factor_bytes_fp64", C.c_int64), ("device_bytes", C.c_int64),
+                ("setup_ms", C.c_double), ("grid_blocks", C.c_int32), ("block_waves", C.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads the HIP library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run python -m paper_2501_08293_amd.build)")
+    # PyTorch ships its own HIP runtime under the same soname; loading PyTorch
+    # first makes the library bind to that one, so the process holds a single
+    # HIP runtime whose device memory and streams both sides share.
+    import torch  # noqa: F401
+    lib = C.CDLL(path)
+    H = C.c_void_p
+    lib.opf_admm_default_options.argtypes = [C.POINTER(opf_admm_options)]
+    lib.opf_admm_default_options.restype = None
+    lib.opf_admm_setup.argtypes = [C.POINTER(opf_problem), C.POINTER(opf_admm_options), C.c_void_p, C.POINTER(H)]
+    lib.opf_admm_setup.restype = C.c_int
+    lib.opf_admm_solve.argtypes = [H, C.POINTER(opf_warm), C.POINTER(opf_result)]
+    lib.opf_admm_solve.restype = C.c_int
+    lib.opf_admm_run_fixed.argtypes = [H, C.POINTER(opf_warm), C.c_int64, C.POINTER(opf_result)]
+    lib.opf_admm_run_fixed.restype = C.c_int
+    lib.opf_admm_residuals.argtypes = [H, C.POINTER(opf_residuals), C.POINTER(C.c_double), C.c_int]
+    lib.opf_admm_residuals.restype = C.c_int
+    lib.opf_admm_get_info.argtypes = [H, C.POINTER(opf_admm_info)]
+    lib.opf_admm_get_info.restype = C.c_int
+    lib.opf_admm_destroy.argtypes = [H]
+    lib.opf_admm_destroy.restype = None
+    lib.opf_admm_last_error.argtypes = [H]
+    lib.opf_admm_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class OpfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _dev_ptr(t):
+    """Device pointer of a torch tensor (or an int address)."""
+    if isinstance(t, int):
+        return t
+    return int(t.data_ptr())
+
+
+# ---- thin wrappers with the C names ------------------------------------------
+
+def opf_admm_default_options() -> opf_admm_options:
+    o = opf_admm_options()
+    load().opf_admm_default_options(C.byref(o))
+    return o
+
+
+def opf_admm_setup(problem: opf_problem, options: opf_admm_options, stream: int = 0):
+    lib = load()
+    h = C.c_void_p()
+    rc = lib.opf_admm_setup(C.byref(problem), C.byref(options), C.c_void_p(stream or None), C.byref(h))
+    if rc != OPF_OK:
+        raise OpfError(rc, lib.opf_admm_last_error(None).decode())
+    return h
+
+
+def opf_admm_solve(h, warm, result: opf_result) -> int:
+    return load().opf_admm_solve(h, C.byref(warm) if warm is not None else None, C.byref(result))
+
+
+def opf_admm_run_fixed(h, warm, iters: int, result: opf_result) -> int:
+    return load().opf_admm_run_fixed(h, C.byref(warm) if warm is not None else None, int(iters), C.byref(result))
+
+
+def opf_admm_residuals(h, hist_cap: int = 0):
+    res = opf_residuals()
+    hist = np.zeros((max(hist_cap, 1), 4))
+    rows = load().opf_admm_residuals(h, C.byref(res), _ptr(hist, C.c_double) if hist_cap else None, hist_cap)
+    if rows < 0:
+        raise OpfError(rows, load().opf_admm_last_error(h).decode())
+    return res, hist[:rows]
+
+
+def opf_admm_get_info(h) -> opf_admm_info:
+    info = opf_admm_info()
+    load().opf_admm_get_info(h, C.byref(info))
+    return info
+
+
+def opf_admm_destroy(h) -> None:
+    load().opf_admm_destroy(h)
+
+
+def opf_admm_last_error(h=None) -> str:
+    return load().opf_admm_last_error(h).decode()
+
+
+# ---- convenience object ---------------------------------------------------------
+
+class Solver:
+    """Owns one handle.  Arrays are those of the opf_problem struct (the
+    componentwise LP of the paper's reformulated model)."""
+
+    def __init__(self, n, c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx, *, rho=100.0,
+                 eps_rel=1e-3, max_iter=1_000_000, precision=OPF_PREC_FP64, polish=True, check_every=256,
+                 kernel=OPF_KERNEL_AUTO, history_cap=0, block_waves=0, stream=0):
+        self._keep = dict(
+            c=np.ascontiguousarray(c, np.float64), lb=np.ascontiguousarray(lb, np.float64),
+            ub=np.ascontiguousarray(ub, np.float64), var_kind=np.ascontiguousarray(var_kind, np.uint8),
+            comp_m=np.ascontiguousarray(comp_m, np.int32), comp_n=np.ascontiguousarray(comp_n, np.int32),
+            A=np.ascontiguousarray(A_vals, np.float64), b=np.ascontiguousarray(b_vals, np.float64),
+            idx=np.ascontiguousarray(idx, np.int32))
+        k = self._keep
+        self.n = int(n)
+        self.L = int(k["comp_n"].sum())
+        p = opf_problem(n=self.n, c=_ptr(k["c"], C.c_double), lb=_ptr(k["lb"], C.c_double),
+                        ub=_ptr(k["ub"], C.c_double), var_kind=_ptr(k["var_kind"], C.c_uint8),
+                        S=len(k["comp_m"]), comp_m=_ptr(k["comp_m"], C.c_int32),
+                        comp_n=_ptr(k["comp_n"], C.c_int32), A_vals=_ptr(k["A"], C.c_double),
+                        b_vals=_ptr(k["b"], C.c_double), idx=_ptr(k["idx"], C.c_int32))
+        o = opf_admm_default_options()
+        o.rho = rho
+        o.eps_rel = eps_rel
+        o.max_iter = max_iter
+        o.precision = precision
+        o.polish = int(bool(polish))
+        o.check_every = check_every
+        o.kernel = kernel
+        o.history_cap = history_cap
+        o.block_waves = block_waves
+        self.options = o
+        self.h = opf_admm_setup(p, o, stream)
+        self._keep = None   # the library copied everything it needs
+
+    @classmethod
+    def from_arrays(cls, flat, **kw):
+        return cls(*flat, **kw)
+
+    def close(self):
+        if getattr(self, "h", None):
+            opf_admm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> opf_admm_info:
+        return opf_admm_get_info(self.h)
+
+    def _result(self, x, z, lam):
+        r = opf_result()
+        dev = not isinstance(x, np.ndarray)
+        r.outputs_on_device = int(dev)
+        if dev:
+            r.x = _dev_ptr(x)
+            r.z = _dev_ptr(z) if z is not None else None
+            r.lam = _dev_ptr(lam) if lam is not None else None
+        else:
+            r.x = x.ctypes.data
+            r.z = z.ctypes.data if z is not None else None
+            r.lam = lam.ctypes.data if lam is not None else None
+        return r
+
+    def _warm(self, z0, lam0):
+        if z0 is None:
+            return None
+        w = opf_warm()
+        if isinstance(z0, np.ndarray):
+            self._warm_keep = (np.ascontiguousarray(z0, np.float64), np.ascontiguousarray(lam0, np.float64))
+            w.z = self._warm_keep[0].ctypes.data
+            w.lam = self._warm_keep[1].ctypes.data
+            w.on_device = 0
+        else:
+            w.z = _dev_ptr(z0)
+            w.lam = _dev_ptr(lam0)
+            w.on_device = 1
+        return w
+
+    def solve(self, x=None, z=None, lam=None, z0=None, lam0=None, fixed_iters=None, raise_on_error=True):
+        """Runs Algorithm 1.  Outputs go to the given arrays (numpy = host,
+        torch CUDA tensors = device); by default new host arrays are returned."""
+        if x is None:
+            x = np.zeros(self.n)
+            z = np.zeros(self.L) if z is None else z
+            lam = np.zeros(self.L) if lam is None else lam
+        r = self._result(x, z, lam)
+        w = self._warm(z0, lam0)
+        if fixed_iters is None:
+            rc = opf_admm_solve(self.h, w, r)
+        else:
+            rc = opf_admm_run_fixed(self.h, w, fixed_iters, r)
+        if rc < 0 and raise_on_error:
+            raise OpfError(rc, opf_admm_last_error(self.h))
+        return dict(status=rc, x=x, z=z, lam=lam, iterations=r.iterations, iterations_fp32=r.iterations_fp32,
+                    objective=r.objective, pres=r.pres, dres=r.dres, eps_prim=r.eps_prim, eps_dual=r.eps_dual,
+                    solve_ms=r.solve_ms)
+
+    def residuals(self, hist_cap=0):
+        return opf_admm_residuals(self.h, hist_cap)

@@ -1,0 +1,511 @@
+// C-ABI implementation: handle life cycle, device buffers, solve drivers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/opf_admm.h"
+#include "admm_kernels.h"
+#include "opf_layout.h"
+
+namespace opf {
+template <typename T> hipError_t launch_step(const IterArgs<T>& a, int wpb, hipStream_t st);
+template <typename T>
+hipError_t launch_init(const double* z0, const double* lam0, T* z, T* l, int LP, Ctrl* ctrl,
+                       long long max_iter, int check, hipStream_t st);
+hipError_t launch_promote(const float* z32a, const float* z32b, const float* l32a, const float* l32b,
+                          double* z64a, double* z64b, double* l64a, double* l64b, int LP, Ctrl* ctrl,
+                          long long max_iter, int check, hipStream_t st);
+template <typename T>
+hipError_t launch_output(const T* z0, const T* z1, const T* l0, const T* l1, const T* x0, const T* x1,
+                         const int* user_slot, int LP, int n, const double* c, double* xo, double* zo,
+                         double* lo, Ctrl* ctrl, hipStream_t st);
+}  // namespace opf
+
+using namespace opf;
+
+namespace {
+
+std::mutex g_err_mu;
+std::string g_setup_err;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// Per-precision device state and static per-slot data.
+template <typename T>
+struct PrecState {
+    T* F = nullptr;
+    T* bbar = nullptr;
+    T* lo = nullptr;
+    T* hi = nullptr;
+    T* cost = nullptr;
+    T* z[2] = {nullptr, nullptr};
+    T* l[2] = {nullptr, nullptr};
+    T* x[2] = {nullptr, nullptr};
+};
+
+}  // namespace
+
+struct opf_admm_handle {
+    opf_admm_options opt;
+    hipStream_t user_stream = nullptr;
+    hipStream_t stream = nullptr;   // private stream; calls are synchronous
+    int device = 0;
+    HostLayout lay;
+    int LP = 0;
+    std::vector<DevBuf> bufs;
+    // static layout on device
+    int2* winfo = nullptr;
+    int* var = nullptr;
+    int* meta = nullptr;
+    int* cstart = nullptr;
+    int* ccnt = nullptr;
+    int* clist = nullptr;
+    int* user_slot = nullptr;
+    int* user_to_dev = nullptr;
+    double* z0 = nullptr;          // default initial local copies (device order)
+    double* c = nullptr;           // [n]
+    double* warm_z = nullptr;      // staging for warm starts (device order)
+    double* warm_l = nullptr;
+    double* user_z = nullptr;      // staging for user-order inputs/outputs
+    double* user_l = nullptr;
+    double* xo = nullptr;          // FP64 x output staging [n]
+    double* partials = nullptr;
+    double* hist = nullptr;
+    Ctrl* ctrl = nullptr;
+    Ctrl* ctrl_host = nullptr;     // pinned
+    PrecState<double> s64;
+    PrecState<float> s32;
+    bool has32 = false;
+    int wpb = 4;
+    int grid_blocks = 0;
+    size_t device_bytes = 0;
+    double setup_ms = 0;
+    long long last_iter = 0;
+    int last_prec = OPF_PREC_FP64;
+    std::string err;
+    // graph of `check_every` step launches per precision
+    hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
+    int graph_k = 0;
+};
+
+namespace {
+
+int set_err(opf_admm_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    else {
+        std::lock_guard<std::mutex> lk(g_err_mu);
+        g_setup_err = msg;
+    }
+    return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t _e = (expr);                                                           \
+        if (_e != hipSuccess)                                                             \
+            return set_err(h, OPF_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+template <typename P>
+int dalloc(opf_admm_handle* h, P** out, size_t count) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(count * sizeof(P), 256);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return set_err(h, OPF_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    h->bufs.push_back({p, bytes});
+    h->device_bytes += bytes;
+    *out = static_cast<P*>(p);
+    return 0;
+}
+
+template <typename P, typename Q>
+int upload(opf_admm_handle* h, P** out, const std::vector<Q>& src) {
+    std::vector<P> tmp(src.begin(), src.end());
+    int rc = dalloc(h, out, std::max<size_t>(tmp.size(), 1));
+    if (rc) return rc;
+    if (!tmp.empty()) HIPCHK(hipMemcpyAsync(*out, tmp.data(), tmp.size() * sizeof(P), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+template <typename T>
+int make_prec(opf_admm_handle* h, PrecState<T>& s) {
+    const HostLayout& L = h->lay;
+    int rc;
+    if ((rc = upload(h, &s.F, L.F))) return rc;
+    if ((rc = upload(h, &s.bbar, L.bbar))) return rc;
+    if ((rc = upload(h, &s.lo, L.lo))) return rc;
+    if ((rc = upload(h, &s.hi, L.hi))) return rc;
+    if ((rc = upload(h, &s.cost, L.cost))) return rc;
+    for (int b = 0; b < 2; ++b) {
+        if ((rc = dalloc(h, &s.z[b], h->LP))) return rc;
+        if ((rc = dalloc(h, &s.l[b], h->LP))) return rc;
+        if ((rc = dalloc(h, &s.x[b], L.n))) return rc;
+        HIPCHK(hipMemsetAsync(s.z[b], 0, sizeof(T) * h->LP, h->stream));
+        HIPCHK(hipMemsetAsync(s.l[b], 0, sizeof(T) * h->LP, h->stream));
+        HIPCHK(hipMemsetAsync(s.x[b], 0, sizeof(T) * L.n, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+template <typename T>
+IterArgs<T> iter_args(opf_admm_handle* h, PrecState<T>& s) {
+    IterArgs<T> a;
+    a.F = s.F;
+    a.winfo = h->winfo;
+    a.var = h->var;
+    a.meta = h->meta;
+    a.cstart = h->cstart;
+    a.ccnt = h->ccnt;
+    a.clist = h->clist;
+    a.bbar = s.bbar;
+    a.lo = s.lo;
+    a.hi = s.hi;
+    a.cost = s.cost;
+    a.z0 = s.z[0];
+    a.z1 = s.z[1];
+    a.l0 = s.l[0];
+    a.l1 = s.l[1];
+    a.x0 = s.x[0];
+    a.x1 = s.x[1];
+    a.partials = h->partials;
+    a.ctrl = h->ctrl;
+    a.hist = h->hist;
+    a.hist_cap = h->opt.history_cap;
+    a.waves = h->lay.waves;
+    a.rho = (T)h->opt.rho;
+    a.inv_rho = (T)(1.0 / h->opt.rho);
+    a.rho_d = h->opt.rho;
+    a.eps_rel = h->opt.eps_rel;
+    return a;
+}
+
+// Captures `k` consecutive step launches into an executable graph.
+template <typename T>
+int capture_steps(opf_admm_handle* h, PrecState<T>& s, int k, hipGraphExec_t* out) {
+    IterArgs<T> a = iter_args(h, s);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < k; ++i) {
+        hipError_t e = launch_step<T>(a, h->wpb, h->stream);
+        if (e != hipSuccess) {
+            (void)hipStreamEndCapture(h->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            return set_err(h, OPF_EHIP, std::string("launch during capture: ") + hipGetErrorString(e));
+        }
+    }
+    HIPCHK(hipStreamEndCapture(h->stream, &g));
+    hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return set_err(h, OPF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return 0;
+}
+
+// Runs step launches until the device stop flag is set.  Returns 0 or error.
+template <typename T>
+int run_phase(opf_admm_handle* h, PrecState<T>& s, hipGraphExec_t* graph) {
+    const int k = std::max(1, h->opt.check_every);
+    if (!*graph || h->graph_k != k) {
+        if (*graph) { (void)hipGraphExecDestroy(*graph); *graph = nullptr; }
+        int rc = capture_steps(h, s, k, graph);
+        if (rc) return rc;
+        h->graph_k = k;
+    }
+    for (;;) {
+        HIPCHK(hipGraphLaunch(*graph, h->stream));
+        HIPCHK(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (h->ctrl_host->stop) break;
+    }
+    return 0;
+}
+
+template <typename T>
+int finish_outputs(opf_admm_handle* h, PrecState<T>& s, opf_result* r) {
+    const int n = h->lay.n, L = h->lay.L;
+    double* xo = r->outputs_on_device ? r->x : h->xo;
+    double* zo = r->z ? (r->outputs_on_device ? r->z : h->user_z) : nullptr;
+    double* lo = r->lam ? (r->outputs_on_device ? r->lam : h->user_l) : nullptr;
+    HIPCHK(launch_output<T>(s.z[0], s.z[1], s.l[0], s.l[1], s.x[0], s.x[1], h->user_slot, h->LP, n, h->c, xo,
+                            zo, lo, h->ctrl, h->stream));
+    HIPCHK(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+    if (!r->outputs_on_device) {
+        HIPCHK(hipMemcpyAsync(r->x, h->xo, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+        if (r->z) HIPCHK(hipMemcpyAsync(r->z, h->user_z, sizeof(double) * L, hipMemcpyDeviceToHost, h->stream));
+        if (r->lam) HIPCHK(hipMemcpyAsync(r->lam, h->user_l, sizeof(double) * L, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+__global__ void scatter_user_kernel(const double* zu, const double* lu, const int* user_to_dev, int L,
+                                    double* zd, double* ld) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < L) {
+        const int d = user_to_dev[u];
+        zd[d] = zu[u];
+        ld[d] = lu[u];
+    }
+}
+
+// Start point in device order (default or warm), as FP64 arrays.
+int prepare_start(opf_admm_handle* h, const opf_warm* warm, const double** z0, const double** l0) {
+    if (!warm) {
+        *z0 = h->z0;
+        *l0 = nullptr;
+        return 0;
+    }
+    if (!warm->z || !warm->lam) return set_err(h, OPF_EINVAL, "warm start needs both z and lam");
+    const int L = h->lay.L;
+    const double* zu = warm->z;
+    const double* lu = warm->lam;
+    if (!warm->on_device) {
+        HIPCHK(hipMemcpyAsync(h->user_z, warm->z, sizeof(double) * L, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->user_l, warm->lam, sizeof(double) * L, hipMemcpyHostToDevice, h->stream));
+        zu = h->user_z;
+        lu = h->user_l;
+    }
+    HIPCHK(hipMemsetAsync(h->warm_z, 0, sizeof(double) * h->LP, h->stream));
+    HIPCHK(hipMemsetAsync(h->warm_l, 0, sizeof(double) * h->LP, h->stream));
+    hipLaunchKernelGGL(scatter_user_kernel, dim3((L + 255) / 256), dim3(256), 0, h->stream, zu, lu,
+                       h->user_to_dev, L, h->warm_z, h->warm_l);
+    HIPCHK(hipGetLastError());
+    *z0 = h->warm_z;
+    *l0 = h->warm_l;
+    return 0;
+}
+
+int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long long fixed_iters) {
+    if (!h || !r || !r->x) return set_err(h, OPF_EINVAL, "null handle, result or x");
+    auto t0 = std::chrono::steady_clock::now();
+    if (h->user_stream != h->stream) HIPCHK(hipStreamSynchronize(h->user_stream));
+    const double* z0;
+    const double* l0;
+    int rc = prepare_start(h, warm, &z0, &l0);
+    if (rc) return rc;
+    const bool fixed = fixed_iters > 0;
+    const long long max_iter = fixed ? fixed_iters : h->opt.max_iter;
+    const int check = fixed ? 0 : 1;
+    int status = OPF_OK;
+    long long it32 = 0;
+    bool final64 = true;
+    if (h->opt.precision == OPF_PREC_MIXED) {
+        HIPCHK(launch_init<float>(z0, l0, h->s32.z[0], h->s32.l[0], h->LP, h->ctrl, max_iter, check, h->stream));
+        rc = run_phase<float>(h, h->s32, &h->graph32);
+        if (rc) return rc;
+        it32 = h->ctrl_host->iter;
+        status = h->ctrl_host->status;
+        const bool polish = h->opt.polish && !fixed && status != OPF_ENUMERIC;
+        if (polish) {
+            HIPCHK(launch_promote(h->s32.z[0], h->s32.z[1], h->s32.l[0], h->s32.l[1], h->s64.z[0], h->s64.z[1],
+                                  h->s64.l[0], h->s64.l[1], h->LP, h->ctrl, it32 + h->opt.max_iter, 1, h->stream));
+            rc = run_phase<double>(h, h->s64, &h->graph64);
+            if (rc) return rc;
+            status = h->ctrl_host->status;
+        } else {
+            final64 = false;
+        }
+    } else {
+        HIPCHK(launch_init<double>(z0, l0, h->s64.z[0], h->s64.l[0], h->LP, h->ctrl, max_iter, check, h->stream));
+        rc = run_phase<double>(h, h->s64, &h->graph64);
+        if (rc) return rc;
+        status = h->ctrl_host->status;
+    }
+    rc = final64 ? finish_outputs<double>(h, h->s64, r) : finish_outputs<float>(h, h->s32, r);
+    if (rc) return rc;
+    const Ctrl& c = *h->ctrl_host;
+    r->iterations = c.iter;
+    r->iterations_fp32 = it32;
+    r->objective = c.objective;
+    r->pres = c.res[0];
+    r->dres = c.res[1];
+    r->eps_prim = c.res[2];
+    r->eps_dual = c.res[3];
+    r->status = status;
+    h->last_iter = c.iter;
+    h->last_prec = final64 ? OPF_PREC_FP64 : OPF_PREC_MIXED;
+    r->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (status == OPF_ENUMERIC) set_err(h, OPF_ENUMERIC, "NaN/Inf in the residuals");
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+void opf_admm_default_options(opf_admm_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->rho = 100.0;
+    o->eps_rel = 1e-3;
+    o->max_iter = 1000000;
+    o->precision = OPF_PREC_FP64;
+    o->polish = 1;
+    o->check_every = 256;
+    o->kernel = OPF_KERNEL_AUTO;
+    o->history_cap = 0;
+    o->block_waves = 0;
+}
+
+int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_stream, opf_admm_handle** out) {
+    opf_admm_handle* h = nullptr;
+    if (out) *out = nullptr;
+    if (!p || !out) return set_err(nullptr, OPF_EINVAL, "null problem or output pointer");
+    opf_admm_options opt;
+    if (o) opt = *o;
+    else opf_admm_default_options(&opt);
+    if (!(opt.rho > 0.0) || !std::isfinite(opt.rho)) return set_err(nullptr, OPF_EINVAL, "rho must be positive");
+    if (!(opt.eps_rel > 0.0)) return set_err(nullptr, OPF_EINVAL, "eps_rel must be positive");
+    if (opt.max_iter < 1) return set_err(nullptr, OPF_EINVAL, "max_iter must be >= 1");
+    if (opt.precision != OPF_PREC_FP64 && opt.precision != OPF_PREC_MIXED)
+        return set_err(nullptr, OPF_EINVAL, "unknown precision");
+    if (opt.history_cap < 0) return set_err(nullptr, OPF_EINVAL, "history_cap must be >= 0");
+    if (opt.check_every < 1) opt.check_every = 256;
+    auto t0 = std::chrono::steady_clock::now();
+    ProblemView v;
+    v.n = p->n; v.S = p->S; v.c = p->c; v.lb = p->lb; v.ub = p->ub; v.var_kind = p->var_kind;
+    v.comp_m = p->comp_m; v.comp_n = p->comp_n; v.A = p->A_vals; v.b = p->b_vals; v.idx = p->idx;
+    h = new opf_admm_handle();
+    h->opt = opt;
+    std::string err;
+    const int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    int rc = build_layout(v, h->lay, err, threads);
+    if (rc) {
+        delete h;
+        return set_err(nullptr, rc, err);
+    }
+    h->LP = h->lay.waves * kWave;
+    h->user_stream = (hipStream_t)hip_stream;
+    h->wpb = opt.block_waves > 0 ? opt.block_waves : 4;
+    if (h->wpb != 1 && h->wpb != 2 && h->wpb != 4 && h->wpb != 8) h->wpb = 4;
+    auto fail = [&](int code) {
+        std::string m = h->err;
+        opf_admm_destroy(h);
+        return set_err(nullptr, code, m);
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) return fail(set_err(h, OPF_EHIP, "hipGetDevice failed"));
+    if (h->user_stream) {
+        h->stream = h->user_stream;          // all work on the caller's stream
+    } else if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+        return fail(set_err(h, OPF_EHIP, "hipStreamCreate failed"));
+    }
+    if (hipHostMalloc((void**)&h->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
+        return fail(set_err(h, OPF_ENOMEM, "hipHostMalloc failed"));
+    std::memset(h->ctrl_host, 0, sizeof(Ctrl));
+    const HostLayout& L = h->lay;
+    std::vector<int2> wi(L.waves);
+    for (int w = 0; w < L.waves; ++w) wi[w] = make_int2(L.wave_maxn[w], (int)(L.wave_foff[w] / kWave));
+    if ((rc = upload(h, &h->winfo, wi))) return fail(rc);
+    if ((rc = upload(h, &h->var, L.var))) return fail(rc);
+    if ((rc = upload(h, &h->meta, L.meta))) return fail(rc);
+    if ((rc = upload(h, &h->cstart, L.copy_start))) return fail(rc);
+    if ((rc = upload(h, &h->ccnt, L.copy_cnt))) return fail(rc);
+    if ((rc = upload(h, &h->clist, L.copy_list))) return fail(rc);
+    if ((rc = upload(h, &h->user_slot, L.user_slot))) return fail(rc);
+    if ((rc = upload(h, &h->user_to_dev, L.user_to_dev))) return fail(rc);
+    if ((rc = upload(h, &h->z0, L.z0))) return fail(rc);
+    if ((rc = upload(h, &h->c, L.c_full))) return fail(rc);
+    if ((rc = dalloc(h, &h->warm_z, h->LP))) return fail(rc);
+    if ((rc = dalloc(h, &h->warm_l, h->LP))) return fail(rc);
+    if ((rc = dalloc(h, &h->user_z, L.L))) return fail(rc);
+    if ((rc = dalloc(h, &h->user_l, L.L))) return fail(rc);
+    if ((rc = dalloc(h, &h->xo, L.n))) return fail(rc);
+    const int blocks = (L.waves + h->wpb - 1) / h->wpb;
+    h->grid_blocks = blocks;
+    if ((rc = dalloc(h, &h->partials, (size_t)blocks * 5 + 5))) return fail(rc);
+    if ((rc = dalloc(h, &h->hist, (size_t)std::max(1, opt.history_cap) * 4))) return fail(rc);
+    if ((rc = dalloc(h, &h->ctrl, 1))) return fail(rc);
+    if (hipMemsetAsync(h->ctrl, 0, sizeof(Ctrl), h->stream) != hipSuccess) return fail(set_err(h, OPF_EHIP, "memset"));
+    if ((rc = make_prec<double>(h, h->s64))) return fail(rc);
+    if (opt.precision == OPF_PREC_MIXED) {
+        if ((rc = make_prec<float>(h, h->s32))) return fail(rc);
+        h->has32 = true;
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(set_err(h, OPF_EHIP, "sync"));
+    h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return OPF_OK;
+}
+
+int opf_admm_solve(opf_admm_handle* h, const opf_warm* warm, opf_result* r) {
+    return solve_impl(h, warm, r, 0);
+}
+
+int opf_admm_run_fixed(opf_admm_handle* h, const opf_warm* warm, int64_t iters, opf_result* r) {
+    if (iters < 1) return set_err(h, OPF_EINVAL, "iters must be >= 1");
+    return solve_impl(h, warm, r, iters);
+}
+
+int opf_admm_residuals(const opf_admm_handle* hc, opf_residuals* out, double* hist, int hist_cap) {
+    opf_admm_handle* h = const_cast<opf_admm_handle*>(hc);
+    if (!h) return set_err(nullptr, OPF_EINVAL, "null handle");
+    HIPCHK(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const Ctrl& c = *h->ctrl_host;
+    if (out) {
+        out->iterations = c.iter;
+        out->pres = c.res[0];
+        out->dres = c.res[1];
+        out->eps_prim = c.res[2];
+        out->eps_dual = c.res[3];
+    }
+    int rows = 0;
+    if (hist && hist_cap > 0) {
+        rows = (int)std::min<long long>({(long long)hist_cap, (long long)h->opt.history_cap, c.iter});
+        if (rows > 0) {
+            HIPCHK(hipMemcpyAsync(hist, h->hist, sizeof(double) * 4 * rows, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+        }
+    }
+    return rows;
+}
+
+int opf_admm_get_info(const opf_admm_handle* h, opf_admm_info* info) {
+    if (!h || !info) return OPF_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->n = h->lay.n;
+    info->S = h->lay.S;
+    info->L = h->lay.L;
+    info->waves = h->lay.waves;
+    info->lanes = h->LP;
+    info->max_ns = h->lay.max_ns;
+    info->max_copies = h->lay.max_copies;
+    info->sum_ns2 = h->lay.sum_ns2;
+    info->factor_bytes_fp64 = (int64_t)h->lay.F.size() * 8;
+    info->device_bytes = (int64_t)h->device_bytes;
+    info->setup_ms = h->setup_ms;
+    info->grid_blocks = h->grid_blocks;
+    info->block_waves = h->wpb;
+    return 0;
+}
+
+void opf_admm_destroy(opf_admm_handle* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->graph64) (void)hipGraphExecDestroy(h->graph64);
+    if (h->graph32) (void)hipGraphExecDestroy(h->graph32);
+    for (auto& b : h->bufs) (void)hipFree(b.p);
+    if (h->ctrl_host) (void)hipHostFree(h->ctrl_host);
+    if (h->stream && h->stream != h->user_stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+const char* opf_admm_last_error(const opf_admm_handle* h) {
+    if (h) return h->err.c_str();
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    return g_setup_err.c_str();
+}
+
+}  // extern "C"

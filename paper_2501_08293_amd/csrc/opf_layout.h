@@ -1,0 +1,69 @@
+// Host-side data layout of the componentwise ADMM (internal header).
+//
+// Components are packed into 64-lane wavefronts: every lane of a wavefront
+// owns one local slot (one row of its component's projection), a component
+// never straddles two wavefronts, and the factor rows of a wavefront are
+// stored k-major ([k][lane]) so that the k-th column read by all 64 lanes is
+// one contiguous 512-byte (FP64) segment.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace opf {
+
+constexpr int kWave = 64;
+
+struct ProblemView {
+    int32_t n = 0, S = 0;
+    const double* c = nullptr;
+    const double* lb = nullptr;
+    const double* ub = nullptr;
+    const uint8_t* var_kind = nullptr;
+    const int32_t* comp_m = nullptr;
+    const int32_t* comp_n = nullptr;
+    const double* A = nullptr;
+    const double* b = nullptr;
+    const int32_t* idx = nullptr;
+};
+
+struct HostLayout {
+    int32_t n = 0, S = 0, L = 0;
+    int32_t waves = 0;          // packed wavefronts
+    int32_t max_ns = 0, max_copies = 0;
+    int64_t sum_ns2 = 0;
+
+    // per wavefront
+    std::vector<int32_t> wave_maxn;   // columns stored for the wavefront
+    std::vector<int64_t> wave_foff;   // element offset of its factor block
+
+    // per lane (device slot d = wave * 64 + lane); padding lanes have var = -1
+    std::vector<int32_t> var;         // global variable copied by the slot
+    std::vector<int32_t> meta;        // base lane | n_s << 8 | (owner flag) << 16
+    std::vector<int32_t> copy_start;  // offset into copy_list
+    std::vector<int32_t> copy_cnt;    // number of copies of var (N_i)
+    std::vector<int32_t> user_slot;   // user slot order index, -1 for padding
+    std::vector<double>  bbar;        // bbar_s entry of the slot
+    std::vector<double>  lo, hi, cost;   // bounds and objective of var, per slot
+    std::vector<double>  z0;          // default initial local copy (Section V-A)
+
+    std::vector<int32_t> user_to_dev; // [L]
+    std::vector<int32_t> owner_slot;  // [n] device slot that writes x_i
+    std::vector<int32_t> copy_list;   // per slot: all copies of its variable, ascending
+
+    std::vector<double> F;            // packed factors F_s = I - P_s, [k][lane] per wave
+
+    std::vector<double> c_full;       // [n] objective (for c^T x)
+};
+
+// Returns 0 or an OPF_E* code with a message in err.
+int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int threads);
+
+// Factor of one component: F = I - A^T (A A^T)^{-1} A and bbar = A^T (A A^T)^{-1} b
+// from the row-reduced [A | b].  Row-major n x n F.  Returns 0, or
+// OPF_EINFEASIBLE_COMPONENT when row reduction finds 0 = nonzero.
+int component_factor(int m, int n, const double* A, const double* b, double* F, double* bbar,
+                     int* rank_out);
+
+}  // namespace opf

@@ -1,0 +1,120 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+rejects invalid problems during validation (host code, no GPU needed)."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from opfgen import build_instance, make_13bus
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2501_08293_amd import binding
+    return binding, binding.load()
+
+
+def test_library_exports_every_declared_symbol():
+    binding, lib = _lib()
+    hdr = open(os.path.join(ROOT, "include", "opf_admm.h")).read()
+    names = set(re.findall(r"\b(opf_admm_\w+)\s*\(", hdr))
+    assert names, "no declarations found"
+    for nm in sorted(names):
+        assert hasattr(lib, nm), nm
+    assert names == set(binding.EXPORTED)
+
+
+def test_struct_sizes_match_header_layout():
+    binding, _ = _lib()
+    assert C.sizeof(binding.opf_problem) == 88
+    assert C.sizeof(binding.opf_admm_options) == 8 + 8 + 8 + 6 * 4 + 7 * 4 + 4
+    assert C.sizeof(binding.opf_result) == 3 * 8 + 4 + 4 + 8 + 8 + 6 * 8
+
+
+def test_default_options_are_the_papers():
+    binding, _ = _lib()
+    o = binding.opf_admm_default_options()
+    assert o.rho == 100.0 and o.eps_rel == 1e-3 and o.max_iter >= 1
+
+
+def _flat():
+    return list(build_instance(make_13bus(0)).flat())
+
+
+def _setup_expect(code, n, c, lb, ub, kind, cm, cn, A, b, idx):
+    binding, _ = _lib()
+    with pytest.raises(binding.OpfError) as e:
+        binding.Solver(n, c, lb, ub, kind, cm, cn, A, b, idx)
+    assert e.value.code == code, str(e.value)
+
+
+@pytest.fixture(scope="module")
+def inst():
+    return build_instance(make_13bus(0))
+
+
+def test_rejects_lb_above_ub(inst):
+    cm, cn, A, b, idx = inst.flat()
+    lb = inst.lb.copy()
+    ub = inst.ub.copy()
+    k = int(np.nonzero(inst.var_kind == 2)[0][5])
+    lb[k] = ub[k] + 0.1
+    _setup_expect(-2, inst.n, inst.c, lb, ub, inst.var_kind, cm, cn, A, b, idx)
+
+
+def test_rejects_uncovered_variable(inst):
+    cm, cn, A, b, idx = inst.flat()
+    # one more global variable that no component copies
+    _setup_expect(-3, inst.n + 1, np.append(inst.c, 0), np.append(inst.lb, 0), np.append(inst.ub, 0),
+                  np.append(inst.var_kind, 0), cm, cn, A, b, idx)
+
+
+def test_rejects_inconsistent_component(inst):
+    comps = inst.comps
+    A0 = np.vstack([comps[0].A, comps[0].A[:1]])
+    b0 = np.concatenate([comps[0].b, comps[0].b[:1] + 1.0])
+    cm = np.array([A0.shape[0]] + [c.A.shape[0] for c in comps[1:]], np.int32)
+    cn = np.array([c.A.shape[1] for c in comps], np.int32)
+    A = np.concatenate([A0.ravel()] + [c.A.ravel() for c in comps[1:]])
+    b = np.concatenate([b0] + [c.b for c in comps[1:]])
+    idx = np.concatenate([c.idx for c in comps]).astype(np.int32)
+    _setup_expect(-4, inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, cm, cn, A, b, idx)
+
+
+def test_rejects_nan_and_bad_indices(inst):
+    cm, cn, A, b, idx = inst.flat()
+    A2 = A.copy()
+    A2[3] = math.nan
+    _setup_expect(-1, inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, cm, cn, A2, b, idx)
+    idx2 = idx.copy()
+    idx2[1] = idx2[0]      # duplicate inside the first component
+    _setup_expect(-1, inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, cm, cn, A, b, idx2)
+    idx3 = idx.copy()
+    idx3[0] = inst.n       # out of range
+    _setup_expect(-1, inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, cm, cn, A, b, idx3)
+    cn2 = cn.copy()
+    cn2[0] = 65            # wider than a wavefront
+    _setup_expect(-1, inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, cm, cn2, A, b, idx)
+
+
+def test_redundant_consistent_rows_are_accepted_by_validation(inst):
+    """A duplicated consistent row passes validation and row reduction; with
+    no GPU the set-up stops only at the first HIP call."""
+    binding, _ = _lib()
+    comps = inst.comps
+    A0 = np.vstack([comps[0].A, comps[0].A[:1]])
+    b0 = np.concatenate([comps[0].b, comps[0].b[:1]])
+    cm = np.array([A0.shape[0]] + [c.A.shape[0] for c in comps[1:]], np.int32)
+    cn = np.array([c.A.shape[1] for c in comps], np.int32)
+    A = np.concatenate([A0.ravel()] + [c.A.ravel() for c in comps[1:]])
+    b = np.concatenate([b0] + [c.b for c in comps[1:]])
+    idx = np.concatenate([c.idx for c in comps]).astype(np.int32)
+    try:
+        s = binding.Solver(inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, cm, cn, A, b, idx)
+        s.close()
+    except binding.OpfError as e:
+        assert e.code in (-5, -6), str(e)     # only a missing device may stop it

@@ -1,0 +1,209 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 bar (derived from the nonexpansiveness of the ADMM map: per-step
+rounding differences add at most linearly, about t * 1e-16 * scale): iterates
+agree to 1e-9 relative at fixed t; at termination the iteration count agrees
+to +-1 and the objective and voltages to 1e-6 relative.  Mixed-precision bar:
+objective and voltages within 1e-4 relative of the FP64 oracle."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from opfgen import build_instance, by_name
+from oracle import admm
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+RHO = 100.0
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _args(inst):
+    return (inst.n, inst.c, inst.lb, inst.ub, inst.var_kind) + tuple(inst.flat())
+
+
+def _solver(inst, **kw):
+    from paper_2501_08293_amd import Solver
+    return Solver(*_args(inst), **kw)
+
+
+_cache = {}
+
+
+def _inst(name, seed=0):
+    key = (name, seed)
+    if key not in _cache:
+        _cache[key] = build_instance(by_name(name, seed))
+    return _cache[key]
+
+
+def _oracle(name, seed=0):
+    key = ("P", name, seed)
+    if key not in _cache:
+        _cache[key] = admm.setup(_inst(name, seed))
+    return _cache[key]
+
+
+def _golden(name, eps):
+    path = os.path.join(GOLDEN, f"admm_{name}_s0_eps{eps:g}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"golden file {os.path.basename(path)} not written yet")
+    return json.load(open(path))
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b)))))
+
+
+@pytest.mark.parametrize("name", ["13bus", "13bus-zip", "123bus"])
+@pytest.mark.parametrize("t", [1, 10, 100])
+def test_fixed_iteration_state_matches_oracle_fp64(name, t):
+    _say(f"[gpu] fixed-iteration parity {name} t={t} (opf_admm_run_fixed, FP64)")
+    inst = _inst(name)
+    P = _oracle(name)
+    ref = admm.solve(P, rho=RHO, eps_rel=1e-4, fixed_iters=t)
+    s = _solver(inst, rho=RHO, eps_rel=1e-4)
+    out = s.solve(fixed_iters=t)
+    assert out["iterations"] == t
+    assert _rel(out["x"], ref.x) < 1e-9
+    assert _rel(out["z"], ref.z) < 1e-9
+    assert _rel(out["lam"], ref.lam) < 1e-9
+    assert abs(out["pres"] - ref.pres) <= 1e-9 * max(ref.pres, 1e-300) + 1e-14
+    s.close()
+
+
+@pytest.mark.parametrize("name,eps", [("13bus", 1e-4), ("123bus", 1e-4), ("13bus", 1e-3), ("123bus", 1e-3)])
+def test_solve_to_tolerance_matches_golden_fp64(name, eps):
+    _say(f"[gpu] solve-to-tolerance parity {name} eps={eps} (opf_admm_solve, FP64)")
+    g = _golden(name, eps)
+    inst = _inst(name)
+    s = _solver(inst, rho=RHO, eps_rel=eps, check_every=64)
+    out = s.solve()
+    assert out["status"] == 0
+    assert abs(out["iterations"] - g["iterations"]) <= 1
+    assert abs(out["objective"] - g["objective"]) <= 1e-6 * abs(g["objective"])
+    w = out["x"][g["w_index"]]
+    assert np.max(np.abs(w - np.array(g["w_value"]))) <= 1e-6
+    assert out["pres"] <= out["eps_prim"] and out["dres"] <= out["eps_dual"]
+    s.close()
+
+
+def test_residual_trajectory_matches_oracle():
+    """The primal/dual residual history of the GPU run follows the CPU run
+    iteration by iteration (the paper's Fig. 4 comparison on the 13-bus case)."""
+    _say("[gpu] residual history parity 13bus")
+    inst = _inst("13bus")
+    P = _oracle("13bus")
+    ref = admm.solve(P, rho=RHO, eps_rel=1e-4)
+    s = _solver(inst, rho=RHO, eps_rel=1e-4, history_cap=ref.iterations + 10, check_every=32)
+    out = s.solve()
+    res, hist = s.residuals(hist_cap=ref.iterations + 10)
+    assert abs(out["iterations"] - ref.iterations) <= 1
+    k = min(len(hist), len(ref.history))
+    np.testing.assert_allclose(hist[:k], ref.history[:k], rtol=1e-6, atol=1e-12)
+    s.close()
+
+
+def test_solve_zip_delta_variant_matches_oracle():
+    _say("[gpu] 13bus-zip solve parity")
+    inst = _inst("13bus-zip")
+    ref = admm.solve(_oracle("13bus-zip"), rho=RHO, eps_rel=1e-4)
+    s = _solver(inst, rho=RHO, eps_rel=1e-4, check_every=16)
+    out = s.solve()
+    assert abs(out["iterations"] - ref.iterations) <= 1
+    assert abs(out["objective"] - ref.objective) <= 1e-6 * abs(ref.objective)
+    vidx = np.nonzero(inst.var_kind == 2)[0]
+    assert np.max(np.abs(out["x"][vidx] - ref.x[vidx])) <= 1e-6
+    s.close()
+
+
+def test_bitwise_repeatable_and_checkpoint_resume():
+    """Two solves give identical bits; k iterations, export (z, lambda), resume
+    for k more equals 2k iterations bit for bit."""
+    _say("[gpu] determinism + checkpoint/resume 123bus")
+    inst = _inst("123bus")
+    s = _solver(inst, rho=RHO, eps_rel=1e-4)
+    a = s.solve(fixed_iters=300)
+    b = s.solve(fixed_iters=300)
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["z"], b["z"]) and np.array_equal(a["lam"], b["lam"])
+    half = s.solve(fixed_iters=150)
+    rest = s.solve(fixed_iters=150, z0=half["z"], lam0=half["lam"])
+    assert np.array_equal(rest["x"], a["x"]) and np.array_equal(rest["z"], a["z"])
+    assert np.array_equal(rest["lam"], a["lam"])
+    s.close()
+
+
+def test_mixed_precision_matches_fp64_oracle():
+    """FP32 bulk iterations with FP64 residual sums, then FP64 polish: objective
+    and voltages within 1e-4 relative of the FP64 oracle at the same tolerance."""
+    from paper_2501_08293_amd import OPF_PREC_MIXED
+    _say("[gpu] mixed precision 123bus")
+    g = _golden("123bus", 1e-4)
+    inst = _inst("123bus")
+    s = _solver(inst, rho=RHO, eps_rel=1e-4, precision=OPF_PREC_MIXED, check_every=64)
+    out = s.solve()
+    assert out["status"] == 0
+    assert out["iterations_fp32"] > 0
+    assert abs(out["objective"] - g["objective"]) <= 1e-4 * abs(g["objective"])
+    w = out["x"][g["w_index"]]
+    assert np.max(np.abs(w - np.array(g["w_value"])) / np.abs(np.array(g["w_value"]))) <= 1e-4
+    s.close()
+
+
+def test_device_outputs_and_warm_start_from_torch():
+    import torch
+    _say("[gpu] torch device buffers 13bus")
+    inst = _inst("13bus")
+    s = _solver(inst, rho=RHO, eps_rel=1e-4)
+    host = s.solve(fixed_iters=50)
+    dev = torch.device("cuda:0")
+    x = torch.zeros(inst.n, dtype=torch.float64, device=dev)
+    z = torch.zeros(inst.L, dtype=torch.float64, device=dev)
+    lam = torch.zeros(inst.L, dtype=torch.float64, device=dev)
+    out = s.solve(x=x, z=z, lam=lam, fixed_iters=50)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), host["x"])
+    assert np.array_equal(z.cpu().numpy(), host["z"])
+    # warm start from device tensors equals warm start from host arrays
+    z0 = torch.from_numpy(host["z"]).to(dev)
+    l0 = torch.from_numpy(host["lam"]).to(dev)
+    a = s.solve(fixed_iters=20, z0=z0, lam0=l0)
+    b = s.solve(fixed_iters=20, z0=host["z"], lam0=host["lam"])
+    assert np.array_equal(a["x"], b["x"])
+    s.close()
+
+
+def test_full_size_8500bus_fixed_iterations_match_oracle():
+    """At the full 8500-bus size, in the launch configuration the benchmark
+    times: the state after 20 iterations equals the oracle's."""
+    _say("[gpu] 8500bus fixed-iteration parity t=20")
+    inst = _inst("8500bus")
+    P = _oracle("8500bus")
+    ref = admm.solve(P, rho=RHO, eps_rel=1e-4, fixed_iters=20)
+    s = _solver(inst, rho=RHO, eps_rel=1e-4)
+    out = s.solve(fixed_iters=20)
+    assert _rel(out["x"], ref.x) < 1e-9
+    assert _rel(out["z"], ref.z) < 1e-9
+    assert _rel(out["lam"], ref.lam) < 1e-9
+    s.close()
+
+
+def test_full_size_8500bus_solve_matches_golden_fp64():
+    _say("[gpu] 8500bus solve to 1e-4 vs golden (FP64)")
+    g = _golden("8500bus", 1e-4)
+    inst = _inst("8500bus")
+    s = _solver(inst, rho=RHO, eps_rel=1e-4, check_every=512)
+    out = s.solve()
+    assert out["status"] == 0
+    assert abs(out["iterations"] - g["iterations"]) <= 1
+    assert abs(out["objective"] - g["objective"]) <= 1e-6 * abs(g["objective"])
+    w = out["x"][g["w_index"]]
+    assert np.max(np.abs(w - np.array(g["w_value"]))) <= 1e-6
+    s.close()
