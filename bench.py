@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--check-every", type=int, default=1024)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "step", "persistent"])
+    ap.add_argument("--block-waves", type=int, default=0)
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="time this many iterations per step instead of solving to tolerance")
     return ap.parse_args()
@@ -87,8 +89,9 @@ def main():
     stream = torch.cuda.Stream()
     prec = OPF_PREC_MIXED if args.precision == "mixed" else OPF_PREC_FP64
     flat = (inst.n, inst.c, inst.lb, inst.ub, inst.var_kind) + tuple(inst.flat())
+    kern = {"auto": 0, "step": 1, "persistent": 2}[args.kernel]
     solver = Solver(*flat, rho=100.0, eps_rel=args.eps, precision=prec, check_every=args.check_every,
-                    stream=stream.cuda_stream)
+                    kernel=kern, block_waves=args.block_waves, stream=stream.cuda_stream)
     info = solver.info()
     x = torch.zeros(inst.n, dtype=torch.float64, device=dev)
     fixed = args.fixed_iters or None
@@ -142,6 +145,9 @@ def main():
             "generator_s": round(gen_s, 2),
             "waves": info.waves,
             "lanes": info.lanes,
+            "kernel": {1: "step", 2: "persistent"}.get(info.kernel, "?"),
+            "block_waves": info.block_waves,
+            "workgroups": info.grid_blocks,
         },
         "roofline": {
             "bound": "hbm",

@@ -108,8 +108,11 @@ typedef struct opf_admm_options {
     int32_t check_every;    /* STEP schedule: iterations enqueued between host checks of the stop flag */
     int32_t kernel;         /* OPF_KERNEL_* */
     int32_t history_cap;    /* per-iteration residual history kept on the device (0 = none) */
-    int32_t block_waves;    /* wavefronts per workgroup (0 = autotuned) */
-    int32_t reserved[7];
+    int32_t block_waves;    /* wavefronts per workgroup: 1, 2, 4 or 8 (0 = default) */
+    int32_t spin_limit;     /* PERSISTENT: polls before a device-side wait gives up with
+                               OPF_EHANG (0 = default, several seconds) */
+    int32_t split_terms;    /* batched path: bfloat16 terms per operand on MFMA, 2 or 3 (0 = 3) */
+    int32_t reserved[5];
 } opf_admm_options;
 
 /* Optional warm start: z0 and lambda0 in user slot order (length L). */
@@ -151,8 +154,12 @@ typedef struct opf_admm_info {
     int64_t factor_bytes_fp64; /* device bytes of the packed FP64 factors */
     int64_t device_bytes;      /* all device memory owned by the handle */
     double  setup_ms;          /* host factorisation + packing + upload */
-    int32_t grid_blocks;       /* persistent schedule: co-resident workgroups */
-    int32_t block_waves;
+    int32_t grid_blocks;       /* workgroups of the iteration kernels */
+    int32_t block_waves;       /* wavefronts per workgroup */
+    int32_t kernel;            /* OPF_KERNEL_STEP or OPF_KERNEL_PERSISTENT, as selected */
+    int32_t persistent_capacity;   /* co-resident workgroups the device can hold */
+    int32_t max_neighbours;    /* largest number of workgroups one workgroup waits on */
+    int32_t reserved[5];
 } opf_admm_info;
 
 typedef struct opf_admm_handle opf_admm_handle;
@@ -198,6 +205,54 @@ int opf_admm_residuals(const opf_admm_handle* h, opf_residuals* out, double* his
 
 /* Copies layout and size information of the handle. */
 int opf_admm_get_info(const opf_admm_handle* h, opf_admm_info* info);
+
+/*
+ * ---- Batched same-topology scenarios ----------------------------------------
+ *
+ * K scenarios share the problem's topology and every A_s (constant-power loads
+ * keep A_s scenario-independent) and differ in their right-hand sides b_s, so
+ * they share the projection factors F_s and each has its own bbar_s (closed_2).
+ * The local updates of all scenarios then form small dense products
+ * F_s [v_1 ... v_K], evaluated on MFMA in bfloat16 split terms with FP32
+ * accumulation; state is FP32, residual sums FP64.  Each scenario stops at its
+ * own termination test (Section III-C); its x is recorded at that iteration.
+ */
+typedef struct opf_admm_batch opf_admm_batch;
+
+typedef struct opf_batch_result {
+    double*  x;                /* [K][n] scenario-major, required; host or device per the flag */
+    int32_t  outputs_on_device;
+    int32_t  reserved0;
+    int64_t* iterations;       /* [K] host, nullable: stop iteration of each scenario */
+    double*  objective;        /* [K] host, nullable: c^T x of each scenario */
+    int32_t* status;           /* [K] host, nullable: OPF_OK / OPF_NOT_CONVERGED / OPF_ENUMERIC */
+    double*  pres;             /* [K] host, nullable; also dres, eps_prim, eps_dual */
+    double*  dres;
+    double*  eps_prim;
+    double*  eps_dual;
+    int64_t  total_iterations; /* iterations the batch ran (the slowest scenario) */
+    int32_t  converged;        /* scenarios whose test held */
+    int32_t  reserved1;
+    double   solve_ms;
+} opf_batch_result;
+
+/*
+ * Like opf_admm_setup for K scenarios: b_scen holds K concatenated right-hand
+ * sides ([K][sum m_s], host, caller-owned, read during the call).  p->b_vals
+ * may be NULL.  Each scenario's b must be consistent with its A_s
+ * (OPF_EINFEASIBLE_COMPONENT otherwise).  1 <= K <= 4096.
+ */
+int opf_admm_setup_batch(const opf_problem* p, const double* b_scen, int32_t K, const opf_admm_options* o,
+                         void* hip_stream, opf_admm_batch** out);
+
+/* Runs Algorithm 1 for all scenarios from the default start point until every
+   scenario has met its test or max_iter.  Returns OPF_OK when all converged,
+   OPF_NOT_CONVERGED if some reached max_iter, OPF_ENUMERIC, or an error. */
+int opf_admm_solve_batch(opf_admm_batch* h, opf_batch_result* r);
+
+int opf_admm_batch_info(const opf_admm_batch* h, opf_admm_info* info);
+void opf_admm_destroy_batch(opf_admm_batch* h);
+const char* opf_admm_batch_last_error(const opf_admm_batch* h);
 
 /* Frees the handle and its device memory.  NULL is ignored. */
 void opf_admm_destroy(opf_admm_handle* h);

@@ -178,7 +178,7 @@ def _equations(f: Feeder, V: _Vars):
                     cw = -ref * ex / 2.0 * wmul
                     if cw != 0.0:
                         co[V[("w", i, ph)]] = cw
-                    eqs.append((own, co, ref - ref * ex / 2.0))
+                    eqs.append((own, co, ref - ref * ex / 2.0, ("load", l, dq, ph)))
             if ld.conn == "wye":
                 for ph in ld.phases:
                     eqs.append((own, {V[("pb", l, ph)]: 1.0, V[("pd", l, ph)]: -1.0}, 0.0))
@@ -240,27 +240,32 @@ def build_instance(f: Feeder) -> Instance:
                 owner_of_bus[b] = ("line", e)
     groups = {}
     order = []
-    for own, co, rhs in eqs:
+    for own, co, rhs, *tag in eqs:
         if own[0] == "bus" and own[1] in owner_of_bus:
             own = owner_of_bus[own[1]]
         if own not in groups:
             groups[own] = []
             order.append(own)
-        groups[own].append((co, rhs))
+        groups[own].append((co, rhs, tag[0] if tag else None))
     # components in network order: buses first (by id), then lines (by id)
     order.sort(key=lambda o: (0 if o[0] == "bus" else 1, o[1]))
     comps = []
+    load_rows = []          # (row offset in the stacked b, load id) of every VDLM-1/2 row
+    boff = 0
     for own in order:
         rows = groups[own]
-        cols = sorted({j for co, _ in rows for j, v in co.items() if v != 0.0})
+        cols = sorted({j for co, _, _ in rows for j, v in co.items() if v != 0.0})
         pos = {j: k for k, j in enumerate(cols)}
         A = np.zeros((len(rows), len(cols)))
         b = np.zeros(len(rows))
-        for r, (co, rhs) in enumerate(rows):
+        for r, (co, rhs, tag) in enumerate(rows):
             for j, v in co.items():
                 if v != 0.0:
                     A[r, pos[j]] += v
             b[r] = rhs
+            if tag is not None:
+                load_rows.append((boff + r, tag[1]))
+        boff += len(rows)
         kind = own[0]
         if own[0] == "line":
             ln = f.lines[own[1]]
@@ -268,10 +273,44 @@ def build_instance(f: Feeder) -> Instance:
                 kind = "leaf+line"
         comps.append(Component(kind=kind, ident=own, A=A, b=b, idx=np.asarray(cols, dtype=np.int64)))
     n = len(V.keys)
-    return Instance(name=f.name, n=n, c=np.asarray(V.cost, dtype=np.float64),
+    inst = Instance(name=f.name, n=n, c=np.asarray(V.cost, dtype=np.float64),
                     lb=np.asarray(V.lb, dtype=np.float64), ub=np.asarray(V.ub, dtype=np.float64),
                     var_kind=np.asarray(V.kind, dtype=np.uint8), var_keys=list(V.keys), comps=comps,
                     feeder=f)
+    inst.load_rows = np.asarray(load_rows, dtype=np.int64).reshape(-1, 2)
+    return inst
+
+
+def scenario_rhs(inst: Instance, bus_factors: np.ndarray) -> np.ndarray:
+    """Right-hand sides of load scenarios on one topology: scenario k scales the
+    reference powers of every load at bus i by bus_factors[k, i].  Valid for
+    constant-power loads (alpha = beta = 0), whose equations then keep the
+    same A_s and change only b_s.  Returns [K, sum m_s]."""
+    f = inst.feeder
+    for ld in f.loads:
+        if np.any(ld.alpha != 0) or np.any(ld.beta != 0):
+            raise ValueError("load scenarios with a shared A_s need constant-power loads")
+    base = np.concatenate([c.b for c in inst.comps])
+    K = bus_factors.shape[0]
+    out = np.repeat(base[None, :], K, axis=0)
+    rows = inst.load_rows[:, 0]
+    buses = np.array([f.loads[l].bus for l in inst.load_rows[:, 1]], dtype=np.int64)
+    out[:, rows] = base[rows][None, :] * bus_factors[:, buses]
+    return out
+
+
+def with_rhs(inst: Instance, b: np.ndarray) -> Instance:
+    """A copy of the instance whose stacked right-hand side is b."""
+    comps = []
+    o = 0
+    for c in inst.comps:
+        m = c.A.shape[0]
+        comps.append(Component(kind=c.kind, ident=c.ident, A=c.A, b=np.array(b[o:o + m]), idx=c.idx))
+        o += m
+    new = Instance(name=inst.name, n=inst.n, c=inst.c, lb=inst.lb, ub=inst.ub, var_kind=inst.var_kind,
+                   var_keys=inst.var_keys, comps=comps, feeder=inst.feeder)
+    new.load_rows = getattr(inst, "load_rows", None)
+    return new
 
 
 def instance_from_flat(name, n, c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx) -> Instance:

@@ -36,7 +36,9 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBOUNDS", -3: "E
                 -4: "EINFEASIBLE_COMPONENT", -5: "ENOMEM", -6: "EHIP", -7: "ENUMERIC", -8: "EHANG"}
 
 EXPORTED = ["opf_admm_default_options", "opf_admm_setup", "opf_admm_solve", "opf_admm_run_fixed",
-            "opf_admm_residuals", "opf_admm_get_info", "opf_admm_destroy", "opf_admm_last_error"]
+            "opf_admm_residuals", "opf_admm_get_info", "opf_admm_destroy", "opf_admm_last_error",
+            "opf_admm_setup_batch", "opf_admm_solve_batch", "opf_admm_batch_info", "opf_admm_destroy_batch",
+            "opf_admm_batch_last_error"]
 
 
 class opf_problem(C.Structure):
@@ -51,7 +53,7 @@ class opf_admm_options(C.Structure):
     _fields_ = [("rho", C.c_double), ("eps_rel", C.c_double), ("max_iter", C.c_int64),
                 ("precision", C.c_int32), ("polish", C.c_int32), ("check_every", C.c_int32),
                 ("kernel", C.c_int32), ("history_cap", C.c_int32), ("block_waves", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("spin_limit", C.c_int32), ("split_terms", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class opf_warm(C.Structure):
@@ -74,7 +76,18 @@ class opf_admm_info(C.Structure):
     _fields_ = [("n", C.c_int32), ("S", C.c_int32), ("L", C.c_int32), ("waves", C.c_int32),
                 ("lanes", C.c_int32), ("max_ns", C.c_int32), ("max_copies", C.c_int32),
                 ("sum_ns2", C.c_int64), ("factor_bytes_fp64", C.c_int64), ("device_bytes", C.c_int64),
-                ("setup_ms", C.c_double), ("grid_blocks", C.c_int32), ("block_waves", C.c_int32)]
+                ("setup_ms", C.c_double), ("grid_blocks", C.c_int32), ("block_waves", C.c_int32),
+                ("kernel", C.c_int32), ("persistent_capacity", C.c_int32), ("max_neighbours", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
+
+
+class opf_batch_result(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("outputs_on_device", C.c_int32), ("reserved0", C.c_int32),
+                ("iterations", C.POINTER(C.c_int64)), ("objective", C.POINTER(C.c_double)),
+                ("status", C.POINTER(C.c_int32)), ("pres", C.POINTER(C.c_double)), ("dres", C.POINTER(C.c_double)),
+                ("eps_prim", C.POINTER(C.c_double)), ("eps_dual", C.POINTER(C.c_double)),
+                ("total_iterations", C.c_int64), ("converged", C.c_int32), ("reserved1", C.c_int32),
+                ("solve_ms", C.c_double)]
 
 
 _lib = None
@@ -109,6 +122,17 @@ def load(path: str = LIB_PATH):
     lib.opf_admm_destroy.restype = None
     lib.opf_admm_last_error.argtypes = [H]
     lib.opf_admm_last_error.restype = C.c_char_p
+    lib.opf_admm_setup_batch.argtypes = [C.POINTER(opf_problem), C.POINTER(C.c_double), C.c_int32,
+                                         C.POINTER(opf_admm_options), C.c_void_p, C.POINTER(H)]
+    lib.opf_admm_setup_batch.restype = C.c_int
+    lib.opf_admm_solve_batch.argtypes = [H, C.POINTER(opf_batch_result)]
+    lib.opf_admm_solve_batch.restype = C.c_int
+    lib.opf_admm_batch_info.argtypes = [H, C.POINTER(opf_admm_info)]
+    lib.opf_admm_batch_info.restype = C.c_int
+    lib.opf_admm_destroy_batch.argtypes = [H]
+    lib.opf_admm_destroy_batch.restype = None
+    lib.opf_admm_batch_last_error.argtypes = [H]
+    lib.opf_admm_batch_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -178,7 +202,114 @@ def opf_admm_last_error(h=None) -> str:
     return load().opf_admm_last_error(h).decode()
 
 
+def opf_admm_setup_batch(problem: opf_problem, b_scen: np.ndarray, options: opf_admm_options, stream: int = 0):
+    lib = load()
+    h = C.c_void_p()
+    b = np.ascontiguousarray(b_scen, np.float64)
+    rc = lib.opf_admm_setup_batch(C.byref(problem), _ptr(b, C.c_double), int(b.shape[0]), C.byref(options),
+                                  C.c_void_p(stream or None), C.byref(h))
+    if rc != OPF_OK:
+        raise OpfError(rc, lib.opf_admm_batch_last_error(None).decode())
+    return h
+
+
+def opf_admm_solve_batch(h, result: opf_batch_result) -> int:
+    return load().opf_admm_solve_batch(h, C.byref(result))
+
+
+def opf_admm_batch_info(h) -> opf_admm_info:
+    info = opf_admm_info()
+    load().opf_admm_batch_info(h, C.byref(info))
+    return info
+
+
+def opf_admm_destroy_batch(h) -> None:
+    load().opf_admm_destroy_batch(h)
+
+
+def opf_admm_batch_last_error(h=None) -> str:
+    return load().opf_admm_batch_last_error(h).decode()
+
+
 # ---- convenience object ---------------------------------------------------------
+
+
+def _problem(keep, n):
+    return opf_problem(n=int(n), c=_ptr(keep["c"], C.c_double), lb=_ptr(keep["lb"], C.c_double),
+                       ub=_ptr(keep["ub"], C.c_double), var_kind=_ptr(keep["var_kind"], C.c_uint8),
+                       S=len(keep["comp_m"]), comp_m=_ptr(keep["comp_m"], C.c_int32),
+                       comp_n=_ptr(keep["comp_n"], C.c_int32), A_vals=_ptr(keep["A"], C.c_double),
+                       b_vals=_ptr(keep["b"], C.c_double), idx=_ptr(keep["idx"], C.c_int32))
+
+
+def _keep(c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx):
+    return dict(c=np.ascontiguousarray(c, np.float64), lb=np.ascontiguousarray(lb, np.float64),
+                ub=np.ascontiguousarray(ub, np.float64), var_kind=np.ascontiguousarray(var_kind, np.uint8),
+                comp_m=np.ascontiguousarray(comp_m, np.int32), comp_n=np.ascontiguousarray(comp_n, np.int32),
+                A=np.ascontiguousarray(A_vals, np.float64), b=np.ascontiguousarray(b_vals, np.float64),
+                idx=np.ascontiguousarray(idx, np.int32))
+
+
+class BatchSolver:
+    """Owns one batched handle: K right-hand sides b_scen[K, sum m_s] on the
+    topology and A_s of the given problem arrays."""
+
+    def __init__(self, n, c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx, b_scen, *, rho=100.0,
+                 eps_rel=1e-4, max_iter=1_000_000, check_every=64, split_terms=3, stream=0):
+        keep = _keep(c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx)
+        self.n = int(n)
+        self.K = int(np.asarray(b_scen).shape[0])
+        o = opf_admm_default_options()
+        o.rho = rho
+        o.eps_rel = eps_rel
+        o.max_iter = max_iter
+        o.check_every = check_every
+        o.split_terms = split_terms
+        self.h = opf_admm_setup_batch(_problem(keep, n), b_scen, o, stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            opf_admm_destroy_batch(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> opf_admm_info:
+        return opf_admm_batch_info(self.h)
+
+    def solve(self, x=None, raise_on_error=True):
+        K, n = self.K, self.n
+        r = opf_batch_result()
+        if x is None:
+            x = np.zeros((K, n))
+        dev = not isinstance(x, np.ndarray)
+        r.outputs_on_device = int(dev)
+        r.x = _dev_ptr(x) if dev else x.ctypes.data
+        it = np.zeros(K, np.int64)
+        obj = np.zeros(K)
+        st = np.zeros(K, np.int32)
+        pres = np.zeros(K)
+        dres = np.zeros(K)
+        ep = np.zeros(K)
+        ed = np.zeros(K)
+        r.iterations = _ptr(it, C.c_int64)
+        r.objective = _ptr(obj, C.c_double)
+        r.status = _ptr(st, C.c_int32)
+        r.pres = _ptr(pres, C.c_double)
+        r.dres = _ptr(dres, C.c_double)
+        r.eps_prim = _ptr(ep, C.c_double)
+        r.eps_dual = _ptr(ed, C.c_double)
+        rc = opf_admm_solve_batch(self.h, r)
+        if rc < 0 and raise_on_error:
+            raise OpfError(rc, opf_admm_batch_last_error(self.h))
+        return dict(status=rc, x=x, iterations=it, objective=obj, scenario_status=st, pres=pres, dres=dres,
+                    eps_prim=ep, eps_dual=ed, total_iterations=r.total_iterations, converged=r.converged,
+                    solve_ms=r.solve_ms)
+
 
 class Solver:
     """Owns one handle.  Arrays are those of the opf_problem struct (the
@@ -186,7 +317,7 @@ class Solver:
 
     def __init__(self, n, c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx, *, rho=100.0,
                  eps_rel=1e-3, max_iter=1_000_000, precision=OPF_PREC_FP64, polish=True, check_every=256,
-                 kernel=OPF_KERNEL_AUTO, history_cap=0, block_waves=0, stream=0):
+                 kernel=OPF_KERNEL_AUTO, history_cap=0, block_waves=0, spin_limit=0, stream=0):
         self._keep = dict(
             c=np.ascontiguousarray(c, np.float64), lb=np.ascontiguousarray(lb, np.float64),
             ub=np.ascontiguousarray(ub, np.float64), var_kind=np.ascontiguousarray(var_kind, np.uint8),
@@ -211,6 +342,7 @@ class Solver:
         o.kernel = kernel
         o.history_cap = history_cap
         o.block_waves = block_waves
+        o.spin_limit = spin_limit
         self.options = o
         self.h = opf_admm_setup(p, o, stream)
         self._keep = None   # the library copied everything it needs

@@ -1,0 +1,294 @@
+// Batched same-topology scenarios on MFMA (gfx950).
+//
+// K load scenarios share every A_s (constant-power loads), so they share the
+// projection factors F_s and differ only in bbar_s.  One iteration of
+// Algorithm 1 for all scenarios at once:
+//   phase 1  per slot and scenario, the clipped consensus average of the slot's
+//            variable (global_sparse) and the projection input
+//            V = B_s x + lambda_s / rho, staged in LDS as a 64-slot x 64-scenario tile;
+//   phase 2  the local update (closed_2) of every component of a packed
+//            wavefront as one dense product Z = F_w V with F_w the 64 x 64
+//            block-diagonal factor of the wavefront: four 32 x 32 output tiles,
+//            one per wave, each accumulated by v_mfma_f32_32x32x16_bf16 over
+//            K = 64 in FP32.  F_w and V are split into bfloat16 terms
+//            (F = F1 + F2 + F3, V likewise) and the products with term order
+//            i + j <= terms + 1 are summed (6 products for 3 terms), which keeps
+//            FP32-level accuracy; a two-term split leaves a rounding floor above
+//            the paper's dual-residual test at 1e-4;
+//   phase 3  z = Z + bbar, the dual update (ADMM-3) and per-scenario FP64
+//            residual partial sums.
+// A second launch reduces the partials per scenario, applies the termination
+// test per scenario and records each scenario's solution at its own stop
+// iteration; the batch runs until every scenario has stopped.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/opf_admm.h"
+#include "admm_kernels.h"
+
+namespace opf {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(const uint16_t (&h)[8]) {
+    bf16x8 r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = __builtin_bit_cast(__bf16, h[i]);
+    return r;
+}
+
+__device__ __forceinline__ double wave_sum_b(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// grid (W, Kp / 64), 256 threads: wavefront w of the packing, scenarios
+// [64 * blockIdx.y, 64 * blockIdx.y + 64)
+__global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
+    if (a.ctrl->stop) return;
+    const long long t = a.ctrl->iter + 1;
+    const bool odd = (t & 1) != 0;
+    const float* zp = odd ? a.z0 : a.z1;
+    const float* lp = odd ? a.l0 : a.l1;
+    float* zq = odd ? a.z1 : a.z0;
+    float* lq = odd ? a.l1 : a.l0;
+    float* xq = odd ? a.x1 : a.x0;
+    const size_t Kp = (size_t)a.Kp;
+
+    __shared__ float xs[64][65];      // [slot][scenario]
+    __shared__ float vs[64][65];
+    __shared__ double red[4][5][32];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int w = blockIdx.x;
+    const int kc = blockIdx.y * 64;
+
+    // ---- phase 1: consensus average and projection input, 16 slots per wave
+    {
+        const int k = kc + lane;
+#pragma unroll 4
+        for (int rr = 0; rr < 16; ++rr) {
+            const int r = wv * 16 + rr;
+            const int d = w * 64 + r;
+            const int g = a.var[d];
+            float xv = 0.0f, vv = 0.0f;
+            if (g >= 0) {
+                const int cs = a.cstart[d], cn = a.ccnt[d];
+                float acc = 0.0f;
+                for (int q = 0; q < cn; ++q) {
+                    const size_t e = (size_t)a.clist[cs + q];
+                    acc += zp[e * Kp + k] - lp[e * Kp + k] * a.inv_rho;
+                }
+                const float xh = (acc - a.cost[d] * a.inv_rho) / (float)cn;
+                xv = xh < a.lo[d] ? a.lo[d] : (xh > a.hi[d] ? a.hi[d] : xh);
+                vv = xv + lp[(size_t)d * Kp + k] * a.inv_rho;
+                if ((a.meta[d] >> 16) & 1) xq[(size_t)g * Kp + k] = xv;
+            }
+            xs[r][lane] = xv;
+            vs[r][lane] = vv;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 2: Z (64 x 64) = F_w (64 x 64) V (64 x 64); wave wv owns the
+    // 32 x 32 tile (rows 32 m .., scenarios 32 nt ..)
+    const int m = wv & 1, nt = wv >> 1;
+    const int grp = lane >> 5, l32 = lane & 31;
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    const size_t plane = (size_t)a.W * 64 * 64;
+    const uint16_t* Fw = a.Fp + (size_t)w * 64 * 64 + (size_t)(32 * m + l32) * 64;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k0 = 16 * q + 8 * grp;
+        // B operand: V[k0 + i][32 nt + l32], split into bf16 terms
+        uint16_t b1[8], b2[8], b3[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float v = vs[k0 + i][32 * nt + l32];
+            b1[i] = bf16_bits(v);
+            const float r1 = v - bf16_val(b1[i]);
+            b2[i] = bf16_bits(r1);
+            const float r2 = r1 - bf16_val(b2[i]);
+            b3[i] = bf16_bits(r2);
+        }
+        // A operand: F_w[32 m + l32][k0 .. k0 + 7] of each plane (16 bytes)
+        uint16_t a1[8], a2[8], a3[8];
+        {
+            const uint4 u1 = *reinterpret_cast<const uint4*>(Fw + k0);
+            const uint4 u2 = *reinterpret_cast<const uint4*>(Fw + plane + k0);
+            __builtin_memcpy(a1, &u1, 16);
+            __builtin_memcpy(a2, &u2, 16);
+            if (a.terms >= 3) {
+                const uint4 u3 = *reinterpret_cast<const uint4*>(Fw + 2 * plane + k0);
+                __builtin_memcpy(a3, &u3, 16);
+            }
+        }
+        const bf16x8 A1 = as_bf16x8(a1), A2 = as_bf16x8(a2), B1 = as_bf16x8(b1), B2 = as_bf16x8(b2);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B1, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B2, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2, B1, acc, 0, 0, 0);
+        if (a.terms >= 3) {
+            const bf16x8 A3 = as_bf16x8(a3), B3 = as_bf16x8(b3);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B3, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2, B2, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A3, B1, acc, 0, 0, 0);
+        }
+    }
+
+    // ---- phase 3: z = Z + bbar, dual update, residual partials
+    // D[row][col] of a 32 x 32 tile: col = lane % 32, row = 8 (v / 4) + 4 (lane / 32) + v % 4
+    const int col = 32 * nt + l32;
+    const size_t kk = (size_t)(kc + col);
+    double s[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int r = 32 * m + 8 * (v >> 2) + 4 * grp + (v & 3);
+        const size_t d = (size_t)w * 64 + r;
+        if (a.var[d] >= 0) {
+            const float zn = acc[v] + a.bbar[d * Kp + kk];
+            const float xv = xs[r][col];
+            const float zo = zp[d * Kp + kk];
+            const float ln = lp[d * Kp + kk] + a.rho * (xv - zn);
+            zq[d * Kp + kk] = zn;
+            lq[d * Kp + kk] = ln;
+            const double xd = xv, zd = zn;
+            s[0] += (xd - zd) * (xd - zd);
+            s[1] += (zd - (double)zo) * (zd - (double)zo);
+            s[2] += xd * xd;
+            s[3] += zd * zd;
+            s[4] += (double)ln * (double)ln;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) s[i] += __shfl_xor(s[i], 32, 64);
+    if (grp == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) red[wv][i][l32] = s[i];
+    __syncthreads();
+    if (m == 0 && grp == 0) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            a.part[((size_t)i * Kp + kk) * a.W + w] = red[wv][i][l32] + red[wv + 1][i][l32];
+    }
+}
+
+// grid K, 256 threads: reduction of scenario blockIdx.x, its stop decision and
+// the snapshot of its solution; the last workgroup advances the iteration.
+__global__ __launch_bounds__(256) void admm_batch_reduce_kernel(BatchRedArgs r) {
+    BatchCtrl* ctrl = r.ctrl;
+    if (ctrl->stop) return;
+    const long long t = ctrl->iter + 1;
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ double red[4][5];
+    __shared__ int decide;
+    double a[5] = {0, 0, 0, 0, 0};
+    for (int w = threadIdx.x; w < r.W; w += 256)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) a[i] += r.part[((size_t)i * r.Kp + k) * r.W + w];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) a[i] = wave_sum_b(a[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) red[wv][i] = a[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double S[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) S[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+        const double pres = sqrt(S[0]);
+        const double dres = r.rho * sqrt(S[1]);
+        const double ep = r.eps_rel * fmax(sqrt(S[2]), sqrt(S[3]));
+        const double ed = r.eps_rel * sqrt(S[4]);
+        int st = 0;
+        if (r.state[k] == 0) {
+            if (!(isfinite(pres) && isfinite(dres) && isfinite(ep) && isfinite(ed))) st = 3;
+            else if (pres <= ep && dres <= ed) st = 1;
+            else if (t >= ctrl->max_iter) st = 2;
+            if (st) {
+                r.state[k] = st;
+                r.iters[k] = t;
+                r.res[k * 4 + 0] = pres;
+                r.res[k * 4 + 1] = dres;
+                r.res[k * 4 + 2] = ep;
+                r.res[k * 4 + 3] = ed;
+                __hip_atomic_fetch_add(&ctrl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        decide = st;
+    }
+    __syncthreads();
+    if (decide) {
+        // snapshot x of this scenario at its stop iteration and its objective
+        const float* xs = (t & 1) ? r.x1 : r.x0;
+        double obj = 0.0;
+        for (int i = threadIdx.x; i < r.n; i += 256) {
+            const double xv = (double)xs[(size_t)i * r.Kp + k];
+            r.xout[(size_t)k * r.n + i] = xv;
+            obj += r.c[i] * xv;
+        }
+        obj = wave_sum_b(obj);
+        __syncthreads();
+        if (lane == 0) red[wv][0] = obj;
+        __syncthreads();
+        if (threadIdx.x == 0) r.objective[k] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    }
+    if (threadIdx.x == 0) {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const unsigned old = __hip_atomic_fetch_add(&ctrl->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == gridDim.x - 1) {
+            const int done = __hip_atomic_load(&ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ctrl->iter = t;
+            if (done >= r.K || t >= ctrl->max_iter) ctrl->stop = 1;
+            ctrl->arrive = 0u;
+        }
+    }
+}
+
+__global__ void batch_init_kernel(const double* z0, float* z, float* l, int LP, int Kp, BatchCtrl* ctrl,
+                                  int* state, int K, long long max_iter) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t tot = (size_t)LP * Kp;
+    if (i < tot) {
+        z[i] = (float)z0[i / Kp];
+        l[i] = 0.0f;
+    }
+    if (i < (size_t)K) state[i] = 0;
+    if (i == 0) {
+        ctrl->iter = 0;
+        ctrl->max_iter = max_iter;
+        ctrl->stop = 0;
+        ctrl->done = 0;
+        ctrl->arrive = 0u;
+    }
+}
+
+hipError_t launch_batch_iteration(const BatchArgs& a, const BatchRedArgs& r, hipStream_t st) {
+    hipLaunchKernelGGL(admm_batch_step_kernel, dim3(a.W, a.Kp / 64), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(admm_batch_reduce_kernel, dim3(r.K), dim3(256), 0, st, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_init(const double* z0, float* z, float* l, int LP, int Kp, BatchCtrl* ctrl, int* state,
+                             int K, long long max_iter, hipStream_t st) {
+    const size_t tot = (size_t)LP * Kp;
+    hipLaunchKernelGGL(batch_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, z0, z, l, LP, Kp,
+                       ctrl, state, K, max_iter);
+    return hipGetLastError();
+}
+
+}  // namespace opf

@@ -51,11 +51,16 @@ __device__ __forceinline__ void finish_iteration(const double (&s)[5], double* p
         for (int w = 0; w < NT / 64; ++w)
 #pragma unroll
             for (int i = 0; i < 5; ++i) b[i] += red[w][i];
+        // write-through (agent-scope) stores, then wait for them to complete
+        // before arriving; an agent-scope fence would write back the L2 instead
 #pragma unroll
-        for (int i = 0; i < 5; ++i) partials[(size_t)blockIdx.x * 5 + i] = b[i];
-        __threadfence();
-        const unsigned old = atomicAdd(&ctrl->arrive, 1u);
-        __threadfence();
+        for (int i = 0; i < 5; ++i)
+            __hip_atomic_store(&partials[(size_t)blockIdx.x * 5 + i], b[i], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const unsigned old = __hip_atomic_fetch_add(&ctrl->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         is_last = (old == gridDim.x - 1);
     }
     __syncthreads();
@@ -107,7 +112,6 @@ __device__ __forceinline__ void finish_iteration(const double (&s)[5], double* p
         ctrl->status = status;
         ctrl->stop = stop;
         ctrl->arrive = 0u;
-        __threadfence();
     }
 }
 

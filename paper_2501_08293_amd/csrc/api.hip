@@ -24,6 +24,9 @@ hipError_t launch_promote(const float* z32a, const float* z32b, const float* l32
                           double* z64a, double* z64b, double* l64a, double* l64b, int LP, Ctrl* ctrl,
                           long long max_iter, int check, hipStream_t st);
 template <typename T>
+hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G, hipStream_t st);
+template <typename T> int persistent_capacity(int wpb);
+template <typename T>
 hipError_t launch_output(const T* z0, const T* z1, const T* l0, const T* l1, const T* x0, const T* x1,
                          const int* user_slot, int LP, int n, const double* c, double* xo, double* zo,
                          double* lo, Ctrl* ctrl, hipStream_t st);
@@ -97,6 +100,18 @@ struct opf_admm_handle {
     // graph of `check_every` step launches per precision
     hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
     int graph_k = 0;
+    // persistent schedule
+    int kernel = OPF_KERNEL_STEP;
+    int capacity = 0;
+    int* nbr_ptr = nullptr;
+    int* nbr_list = nullptr;
+    long long* flags = nullptr;
+    unsigned* arrive = nullptr;
+    long long* dec_iter = nullptr;
+    int* dec_stop = nullptr;
+    int* dev_error = nullptr;
+    int* stopped = nullptr;
+    int* error_host = nullptr;     // pinned
 };
 
 namespace {
@@ -233,6 +248,39 @@ int run_phase(opf_admm_handle* h, PrecState<T>& s, hipGraphExec_t* graph) {
 }
 
 template <typename T>
+int run_phase_persistent(opf_admm_handle* h, PrecState<T>& s, long long max_iter, int check) {
+    IterArgs<T> a = iter_args(h, s);
+    PersistArgs p;
+    p.nbr_ptr = h->nbr_ptr;
+    p.nbr_list = h->nbr_list;
+    p.flags = h->flags;
+    p.arrive = h->arrive;
+    p.partials = h->partials;
+    p.dec_iter = h->dec_iter;
+    p.dec_stop = h->dec_stop;
+    p.error = h->dev_error;
+    p.stopped = h->stopped;
+    p.spin_limit = h->opt.spin_limit > 0 ? h->opt.spin_limit : 4000000LL;
+    p.max_iter = max_iter;
+    p.check = check;
+    HIPCHK(launch_persistent<T>(a, p, h->wpb, h->lay.blocks, h->stream));
+    HIPCHK(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(h->error_host, h->dev_error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (*h->error_host) {
+        h->ctrl_host->status = OPF_EHANG;
+        return set_err(h, OPF_EHANG, "a bounded device-side wait ran out in the persistent kernel");
+    }
+    return 0;
+}
+
+template <typename T>
+int run_any(opf_admm_handle* h, PrecState<T>& s, hipGraphExec_t* graph, long long max_iter, int check) {
+    if (h->kernel == OPF_KERNEL_PERSISTENT) return run_phase_persistent<T>(h, s, max_iter, check);
+    return run_phase<T>(h, s, graph);
+}
+
+template <typename T>
 int finish_outputs(opf_admm_handle* h, PrecState<T>& s, opf_result* r) {
     const int n = h->lay.n, L = h->lay.L;
     double* xo = r->outputs_on_device ? r->x : h->xo;
@@ -303,7 +351,7 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
     bool final64 = true;
     if (h->opt.precision == OPF_PREC_MIXED) {
         HIPCHK(launch_init<float>(z0, l0, h->s32.z[0], h->s32.l[0], h->LP, h->ctrl, max_iter, check, h->stream));
-        rc = run_phase<float>(h, h->s32, &h->graph32);
+        rc = run_any<float>(h, h->s32, &h->graph32, max_iter, check);
         if (rc) return rc;
         it32 = h->ctrl_host->iter;
         status = h->ctrl_host->status;
@@ -311,7 +359,7 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
         if (polish) {
             HIPCHK(launch_promote(h->s32.z[0], h->s32.z[1], h->s32.l[0], h->s32.l[1], h->s64.z[0], h->s64.z[1],
                                   h->s64.l[0], h->s64.l[1], h->LP, h->ctrl, it32 + h->opt.max_iter, 1, h->stream));
-            rc = run_phase<double>(h, h->s64, &h->graph64);
+            rc = run_any<double>(h, h->s64, &h->graph64, it32 + h->opt.max_iter, 1);
             if (rc) return rc;
             status = h->ctrl_host->status;
         } else {
@@ -319,7 +367,7 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
         }
     } else {
         HIPCHK(launch_init<double>(z0, l0, h->s64.z[0], h->s64.l[0], h->LP, h->ctrl, max_iter, check, h->stream));
-        rc = run_phase<double>(h, h->s64, &h->graph64);
+        rc = run_any<double>(h, h->s64, &h->graph64, max_iter, check);
         if (rc) return rc;
         status = h->ctrl_host->status;
     }
@@ -381,6 +429,8 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     h->opt = opt;
     std::string err;
     const int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    h->lay.block_waves = (opt.block_waves == 1 || opt.block_waves == 2 || opt.block_waves == 4 ||
+                          opt.block_waves == 8) ? opt.block_waves : 4;
     int rc = build_layout(v, h->lay, err, threads);
     if (rc) {
         delete h;
@@ -388,8 +438,7 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     }
     h->LP = h->lay.waves * kWave;
     h->user_stream = (hipStream_t)hip_stream;
-    h->wpb = opt.block_waves > 0 ? opt.block_waves : 4;
-    if (h->wpb != 1 && h->wpb != 2 && h->wpb != 4 && h->wpb != 8) h->wpb = 4;
+    h->wpb = h->lay.block_waves;
     auto fail = [&](int code) {
         std::string m = h->err;
         opf_admm_destroy(h);
@@ -422,9 +471,30 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     if ((rc = dalloc(h, &h->user_z, L.L))) return fail(rc);
     if ((rc = dalloc(h, &h->user_l, L.L))) return fail(rc);
     if ((rc = dalloc(h, &h->xo, L.n))) return fail(rc);
-    const int blocks = (L.waves + h->wpb - 1) / h->wpb;
+    const int blocks = L.blocks;
     h->grid_blocks = blocks;
-    if ((rc = dalloc(h, &h->partials, (size_t)blocks * 5 + 5))) return fail(rc);
+    if ((rc = dalloc(h, &h->partials, (size_t)blocks * 10 + 10))) return fail(rc);
+    if ((rc = upload(h, &h->nbr_ptr, L.nbr_ptr))) return fail(rc);
+    if ((rc = upload(h, &h->nbr_list, L.nbr_list))) return fail(rc);
+    if ((rc = dalloc(h, &h->flags, blocks))) return fail(rc);
+    if ((rc = dalloc(h, &h->arrive, 2))) return fail(rc);
+    if ((rc = dalloc(h, &h->dec_iter, 2))) return fail(rc);
+    if ((rc = dalloc(h, &h->dec_stop, 2))) return fail(rc);
+    if ((rc = dalloc(h, &h->dev_error, 1))) return fail(rc);
+    if ((rc = dalloc(h, &h->stopped, 1))) return fail(rc);
+    if (hipHostMalloc((void**)&h->error_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return fail(set_err(h, OPF_ENOMEM, "hipHostMalloc failed"));
+    *h->error_host = 0;
+    h->capacity = opt.precision == OPF_PREC_MIXED ? std::min(persistent_capacity<float>(h->wpb),
+                                                             persistent_capacity<double>(h->wpb))
+                                                  : persistent_capacity<double>(h->wpb);
+    if (opt.kernel == OPF_KERNEL_PERSISTENT && h->capacity < blocks + 1)
+        return fail(set_err(h, OPF_EINVAL, "persistent kernel needs " + std::to_string(blocks + 1) +
+                                              " co-resident workgroups, the device holds " +
+                                              std::to_string(h->capacity)));
+    if (opt.kernel == OPF_KERNEL_STEP) h->kernel = OPF_KERNEL_STEP;
+    else if (opt.kernel == OPF_KERNEL_PERSISTENT) h->kernel = OPF_KERNEL_PERSISTENT;
+    else h->kernel = (h->capacity >= blocks + 1) ? OPF_KERNEL_PERSISTENT : OPF_KERNEL_STEP;
     if ((rc = dalloc(h, &h->hist, (size_t)std::max(1, opt.history_cap) * 4))) return fail(rc);
     if ((rc = dalloc(h, &h->ctrl, 1))) return fail(rc);
     if (hipMemsetAsync(h->ctrl, 0, sizeof(Ctrl), h->stream) != hipSuccess) return fail(set_err(h, OPF_EHIP, "memset"));
@@ -488,6 +558,9 @@ int opf_admm_get_info(const opf_admm_handle* h, opf_admm_info* info) {
     info->setup_ms = h->setup_ms;
     info->grid_blocks = h->grid_blocks;
     info->block_waves = h->wpb;
+    info->kernel = h->kernel;
+    info->persistent_capacity = h->capacity;
+    info->max_neighbours = h->lay.max_nbrs;
     return 0;
 }
 
@@ -498,6 +571,7 @@ void opf_admm_destroy(opf_admm_handle* h) {
     if (h->graph32) (void)hipGraphExecDestroy(h->graph32);
     for (auto& b : h->bufs) (void)hipFree(b.p);
     if (h->ctrl_host) (void)hipHostFree(h->ctrl_host);
+    if (h->error_host) (void)hipHostFree(h->error_host);
     if (h->stream && h->stream != h->user_stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }

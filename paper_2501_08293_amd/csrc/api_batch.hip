@@ -1,0 +1,292 @@
+// C-ABI of the batched same-topology path (K load scenarios sharing A_s).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/opf_admm.h"
+#include "admm_kernels.h"
+#include "opf_layout.h"
+
+
+using namespace opf;
+
+namespace {
+std::mutex g_berr_mu;
+std::string g_batch_setup_err;
+}  // namespace
+
+struct opf_admm_batch {
+    opf_admm_options opt;
+    hipStream_t user_stream = nullptr;
+    hipStream_t stream = nullptr;
+    HostLayout lay;
+    int K = 0, Kp = 0, LP = 0, terms = 3;
+    std::vector<void*> bufs;
+    size_t device_bytes = 0;
+    double setup_ms = 0;
+    std::string err;
+    uint16_t* Fp = nullptr;
+    int *var = nullptr, *meta = nullptr, *cstart = nullptr, *ccnt = nullptr, *clist = nullptr;
+    float *lo = nullptr, *hi = nullptr, *cost = nullptr, *bbar = nullptr;
+    float* z[2] = {nullptr, nullptr};
+    float* l[2] = {nullptr, nullptr};
+    float* x[2] = {nullptr, nullptr};
+    double* part = nullptr;
+    double* z0 = nullptr;
+    double* c = nullptr;
+    BatchCtrl* ctrl = nullptr;
+    BatchCtrl* ctrl_host = nullptr;
+    int* state = nullptr;
+    long long* iters = nullptr;
+    double* res = nullptr;
+    double* objective = nullptr;
+    double* xout = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_k = 0;
+};
+
+namespace {
+
+int berr(opf_admm_batch* h, int code, const std::string& m) {
+    if (h) h->err = m;
+    else {
+        std::lock_guard<std::mutex> lk(g_berr_mu);
+        g_batch_setup_err = m;
+    }
+    return code;
+}
+
+#define BHIP(expr)                                                                         \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess) return berr(h, OPF_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+template <typename P>
+int balloc(opf_admm_batch* h, P** out, size_t count) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(count * sizeof(P), 256);
+    if (hipMalloc(&p, bytes) != hipSuccess) return berr(h, OPF_ENOMEM, "hipMalloc failed");
+    h->bufs.push_back(p);
+    h->device_bytes += bytes;
+    *out = static_cast<P*>(p);
+    return 0;
+}
+
+template <typename P, typename Q>
+int bupload(opf_admm_batch* h, P** out, const std::vector<Q>& src) {
+    std::vector<P> tmp(src.begin(), src.end());
+    int rc = balloc(h, out, std::max<size_t>(tmp.size(), 1));
+    if (rc) return rc;
+    if (!tmp.empty()) BHIP(hipMemcpyAsync(*out, tmp.data(), tmp.size() * sizeof(P), hipMemcpyHostToDevice, h->stream));
+    BHIP(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+void args_of(opf_admm_batch* h, BatchArgs& a, BatchRedArgs& r) {
+    a.Fp = h->Fp; a.terms = h->terms;
+    a.var = h->var; a.meta = h->meta; a.cstart = h->cstart; a.ccnt = h->ccnt; a.clist = h->clist;
+    a.lo = h->lo; a.hi = h->hi; a.cost = h->cost; a.bbar = h->bbar;
+    a.z0 = h->z[0]; a.z1 = h->z[1]; a.l0 = h->l[0]; a.l1 = h->l[1]; a.x0 = h->x[0]; a.x1 = h->x[1];
+    a.part = h->part; a.ctrl = h->ctrl;
+    a.W = h->lay.waves; a.Kp = h->Kp; a.K = h->K; a.n = h->lay.n;
+    a.rho = (float)h->opt.rho; a.inv_rho = (float)(1.0 / h->opt.rho);
+    r.part = h->part; r.ctrl = h->ctrl; r.state = h->state; r.iters = h->iters; r.res = h->res;
+    r.objective = h->objective; r.xout = h->xout; r.x0 = h->x[0]; r.x1 = h->x[1]; r.c = h->c;
+    r.W = h->lay.waves; r.Kp = h->Kp; r.K = h->K; r.n = h->lay.n;
+    r.rho = h->opt.rho; r.eps_rel = h->opt.eps_rel;
+}
+
+}  // namespace
+
+extern "C" {
+
+int opf_admm_setup_batch(const opf_problem* p, const double* b_scen, int32_t K, const opf_admm_options* o,
+                         void* hip_stream, opf_admm_batch** out) {
+    if (out) *out = nullptr;
+    if (!p || !b_scen || !out) return berr(nullptr, OPF_EINVAL, "null argument");
+    if (K < 1 || K > 4096) return berr(nullptr, OPF_EINVAL, "K must be in [1, 4096]");
+    opf_admm_options opt;
+    if (o) opt = *o;
+    else opf_admm_default_options(&opt);
+    if (!(opt.rho > 0.0) || !(opt.eps_rel > 0.0) || opt.max_iter < 1)
+        return berr(nullptr, OPF_EINVAL, "rho, eps_rel and max_iter must be positive");
+    if (opt.check_every < 1) opt.check_every = 64;
+    auto t0 = std::chrono::steady_clock::now();
+    opf_admm_batch* h = new opf_admm_batch();
+    h->opt = opt;
+    h->K = K;
+    h->Kp = (K + 63) / 64 * 64;
+    h->terms = (opt.split_terms == 2) ? 2 : 3;
+    ProblemView v;
+    v.n = p->n; v.S = p->S; v.c = p->c; v.lb = p->lb; v.ub = p->ub; v.var_kind = p->var_kind;
+    v.comp_m = p->comp_m; v.comp_n = p->comp_n; v.A = p->A_vals; v.b = p->b_vals ? p->b_vals : b_scen;
+    v.idx = p->idx;
+    h->lay.block_waves = 1;
+    std::string err;
+    const int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    int rc = build_layout(v, h->lay, err, threads);
+    std::vector<float> bb;
+    if (!rc) rc = build_batch_rhs(v, h->lay, b_scen, K, h->Kp, bb, err, threads);
+    if (rc) {
+        delete h;
+        return berr(nullptr, rc, err);
+    }
+    h->LP = h->lay.waves * 64;
+    h->user_stream = (hipStream_t)hip_stream;
+    auto fail = [&](int code) {
+        std::string m = h->err;
+        opf_admm_destroy_batch(h);
+        return berr(nullptr, code, m);
+    };
+    if (h->user_stream) h->stream = h->user_stream;
+    else if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(berr(h, OPF_EHIP, "hipStreamCreate failed"));
+    if (hipHostMalloc((void**)&h->ctrl_host, sizeof(BatchCtrl), hipHostMallocDefault) != hipSuccess)
+        return fail(berr(h, OPF_ENOMEM, "hipHostMalloc failed"));
+    const HostLayout& L = h->lay;
+    std::vector<uint16_t> planes;
+    build_dense_planes(L, h->terms, planes);
+    if ((rc = bupload(h, &h->Fp, planes))) return fail(rc);
+    if ((rc = bupload(h, &h->var, L.var))) return fail(rc);
+    if ((rc = bupload(h, &h->meta, L.meta))) return fail(rc);
+    if ((rc = bupload(h, &h->cstart, L.copy_start))) return fail(rc);
+    if ((rc = bupload(h, &h->ccnt, L.copy_cnt))) return fail(rc);
+    if ((rc = bupload(h, &h->clist, L.copy_list))) return fail(rc);
+    if ((rc = bupload(h, &h->lo, L.lo))) return fail(rc);
+    if ((rc = bupload(h, &h->hi, L.hi))) return fail(rc);
+    if ((rc = bupload(h, &h->cost, L.cost))) return fail(rc);
+    if ((rc = bupload(h, &h->bbar, bb))) return fail(rc);
+    if ((rc = bupload(h, &h->z0, L.z0))) return fail(rc);
+    if ((rc = bupload(h, &h->c, L.c_full))) return fail(rc);
+    const size_t st = (size_t)h->LP * h->Kp;
+    for (int b = 0; b < 2; ++b) {
+        if ((rc = balloc(h, &h->z[b], st))) return fail(rc);
+        if ((rc = balloc(h, &h->l[b], st))) return fail(rc);
+        if ((rc = balloc(h, &h->x[b], (size_t)L.n * h->Kp))) return fail(rc);
+        if (hipMemsetAsync(h->x[b], 0, sizeof(float) * (size_t)L.n * h->Kp, h->stream) != hipSuccess)
+            return fail(berr(h, OPF_EHIP, "memset"));
+    }
+    if ((rc = balloc(h, &h->part, (size_t)5 * h->Kp * L.waves))) return fail(rc);
+    if ((rc = balloc(h, &h->ctrl, 1))) return fail(rc);
+    if ((rc = balloc(h, &h->state, K))) return fail(rc);
+    if ((rc = balloc(h, &h->iters, K))) return fail(rc);
+    if ((rc = balloc(h, &h->res, (size_t)4 * K))) return fail(rc);
+    if ((rc = balloc(h, &h->objective, K))) return fail(rc);
+    if ((rc = balloc(h, &h->xout, (size_t)K * L.n))) return fail(rc);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(berr(h, OPF_EHIP, "sync"));
+    h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return OPF_OK;
+}
+
+int opf_admm_solve_batch(opf_admm_batch* h, opf_batch_result* r) {
+    if (!h || !r || !r->x) return berr(h, OPF_EINVAL, "null handle, result or x");
+    auto t0 = std::chrono::steady_clock::now();
+    if (h->user_stream != h->stream && h->user_stream) BHIP(hipStreamSynchronize(h->user_stream));
+    BHIP(launch_batch_init(h->z0, h->z[0], h->l[0], h->LP, h->Kp, h->ctrl, h->state, h->K, h->opt.max_iter,
+                           h->stream));
+    const int k = std::max(1, h->opt.check_every);
+    if (!h->graph || h->graph_k != k) {
+        if (h->graph) { (void)hipGraphExecDestroy(h->graph); h->graph = nullptr; }
+        BatchArgs a;
+        BatchRedArgs rr;
+        args_of(h, a, rr);
+        hipGraph_t g = nullptr;
+        BHIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < k; ++i) {
+            hipError_t e = launch_batch_iteration(a, rr, h->stream);
+            if (e != hipSuccess) {
+                (void)hipStreamEndCapture(h->stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                return berr(h, OPF_EHIP, std::string("launch during capture: ") + hipGetErrorString(e));
+            }
+        }
+        BHIP(hipStreamEndCapture(h->stream, &g));
+        hipError_t e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return berr(h, OPF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        h->graph_k = k;
+    }
+    for (;;) {
+        BHIP(hipGraphLaunch(h->graph, h->stream));
+        BHIP(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, h->stream));
+        BHIP(hipStreamSynchronize(h->stream));
+        if (h->ctrl_host->stop) break;
+    }
+    const int K = h->K, n = h->lay.n;
+    std::vector<int> st(K);
+    std::vector<long long> it(K);
+    std::vector<double> res((size_t)4 * K), obj(K);
+    BHIP(hipMemcpyAsync(st.data(), h->state, sizeof(int) * K, hipMemcpyDeviceToHost, h->stream));
+    BHIP(hipMemcpyAsync(it.data(), h->iters, sizeof(long long) * K, hipMemcpyDeviceToHost, h->stream));
+    BHIP(hipMemcpyAsync(res.data(), h->res, sizeof(double) * 4 * K, hipMemcpyDeviceToHost, h->stream));
+    BHIP(hipMemcpyAsync(obj.data(), h->objective, sizeof(double) * K, hipMemcpyDeviceToHost, h->stream));
+    BHIP(hipMemcpyAsync(r->x, h->xout, sizeof(double) * (size_t)K * n,
+                        r->outputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+    BHIP(hipStreamSynchronize(h->stream));
+    int converged = 0, status = OPF_OK;
+    for (int q = 0; q < K; ++q) {
+        const int code = st[q] == 1 ? OPF_OK : (st[q] == 3 ? OPF_ENUMERIC : OPF_NOT_CONVERGED);
+        if (st[q] == 1) ++converged;
+        if (code == OPF_ENUMERIC) status = OPF_ENUMERIC;
+        else if (code == OPF_NOT_CONVERGED && status == OPF_OK) status = OPF_NOT_CONVERGED;
+        if (r->iterations) r->iterations[q] = it[q];
+        if (r->objective) r->objective[q] = obj[q];
+        if (r->status) r->status[q] = code;
+        if (r->pres) r->pres[q] = res[(size_t)4 * q + 0];
+        if (r->dres) r->dres[q] = res[(size_t)4 * q + 1];
+        if (r->eps_prim) r->eps_prim[q] = res[(size_t)4 * q + 2];
+        if (r->eps_dual) r->eps_dual[q] = res[(size_t)4 * q + 3];
+    }
+    r->total_iterations = h->ctrl_host->iter;
+    r->converged = converged;
+    r->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (status == OPF_ENUMERIC) berr(h, OPF_ENUMERIC, "NaN/Inf in the residuals of a scenario");
+    return status;
+}
+
+int opf_admm_batch_info(const opf_admm_batch* h, opf_admm_info* info) {
+    if (!h || !info) return OPF_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->n = h->lay.n;
+    info->S = h->lay.S;
+    info->L = h->lay.L;
+    info->waves = h->lay.waves;
+    info->lanes = h->LP;
+    info->max_ns = h->lay.max_ns;
+    info->max_copies = h->lay.max_copies;
+    info->sum_ns2 = h->lay.sum_ns2;
+    info->factor_bytes_fp64 = (int64_t)h->lay.F.size() * 8;
+    info->device_bytes = (int64_t)h->device_bytes;
+    info->setup_ms = h->setup_ms;
+    info->grid_blocks = h->lay.waves;
+    info->block_waves = 4;
+    info->kernel = OPF_KERNEL_STEP;
+    return 0;
+}
+
+void opf_admm_destroy_batch(opf_admm_batch* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    for (void* p : h->bufs) (void)hipFree(p);
+    if (h->ctrl_host) (void)hipHostFree(h->ctrl_host);
+    if (h->stream && h->stream != h->user_stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+const char* opf_admm_batch_last_error(const opf_admm_batch* h) {
+    if (h) return h->err.c_str();
+    std::lock_guard<std::mutex> lk(g_berr_mu);
+    return g_batch_setup_err.c_str();
+}
+
+}  // extern "C"

@@ -30,7 +30,10 @@ struct ProblemView {
 
 struct HostLayout {
     int32_t n = 0, S = 0, L = 0;
-    int32_t waves = 0;          // packed wavefronts
+    int32_t waves = 0;          // packed wavefronts (blocks * block_waves, some may be empty)
+    int32_t block_waves = 0;    // wavefronts per workgroup (input: requested, 0 = default)
+    int32_t blocks = 0;         // workgroups
+    int32_t max_nbrs = 0;       // largest neighbour list
     int32_t max_ns = 0, max_copies = 0;
     int64_t sum_ns2 = 0;
 
@@ -54,6 +57,10 @@ struct HostLayout {
 
     std::vector<double> F;            // packed factors F_s = I - P_s, [k][lane] per wave
 
+    // workgroups owning a copy of a variable of workgroup b: nbr_list[nbr_ptr[b] .. nbr_ptr[b+1])
+    std::vector<int32_t> nbr_ptr;
+    std::vector<int32_t> nbr_list;
+
     std::vector<double> c_full;       // [n] objective (for c^T x)
 };
 
@@ -65,5 +72,25 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
 // OPF_EINFEASIBLE_COMPONENT when row reduction finds 0 = nonzero.
 int component_factor(int m, int n, const double* A, const double* b, double* F, double* bbar,
                      int* rank_out);
+
+// The same for r right-hand sides at once: Bm is m x r row-major, bbar n x r.
+// With r_in < 0 the |r_in| right-hand sides are not checked for consistency.
+int component_factor_multi(int m, int n, const double* A, int r_in, const double* Bm, double* F,
+                           double* bbar, int* rank_out);
+
+// Linear map b -> bbar of one component (n x m row-major): bbar = Wmap b for
+// every right-hand side consistent with A.
+int component_rhs_map(int m, int n, const double* A, double* F, double* Wmap);
+
+// Batched scenarios sharing A: bbar of every slot and scenario in device order,
+// [slot][Kp] (scenario-minor, Kp >= K padded with zeros).  b_scen is [K][sum m_s].
+int build_batch_rhs(const ProblemView& p, const HostLayout& lay, const double* b_scen, int K, int Kp,
+                    std::vector<float>& out, std::string& err, int threads);
+
+// Dense block-diagonal 64 x 64 factor of every wavefront (row = output lane,
+// column = input lane), split into `terms` bfloat16 planes whose sum
+// approximates F: plane t holds bf16(F - sum of planes < t).  Layout
+// [terms][wave][64][64].
+void build_dense_planes(const HostLayout& lay, int terms, std::vector<uint16_t>& planes);
 
 }  // namespace opf

@@ -23,16 +23,34 @@ namespace opf {
 
 int component_factor(int m, int n, const double* A, const double* b, double* F, double* bbar,
                      int* rank_out) {
-    const int w = n + 1;
+    return component_factor_multi(m, n, A, 1, b, F, bbar, rank_out);
+}
+
+int component_rhs_map(int m, int n, const double* A, double* F, double* Wmap) {
+    std::vector<double> I((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = 1.0;
+    int rank = 0;
+    // identity right-hand sides: rows that reduce to zero carry the consistency
+    // conditions of b, not a contradiction, so they are not checked here
+    return component_factor_multi(m, n, A, -m, I.data(), F, Wmap, &rank);
+}
+
+int component_factor_multi(int m, int n, const double* A, int r_in, const double* Bm, double* F,
+                           double* bbar, int* rank_out) {
+    const bool check = r_in > 0;
+    const int r = r_in > 0 ? r_in : -r_in;
+    const int w = n + r;
     std::vector<double> M((size_t)m * w);
     double amax = 0.0, bmax = 0.0;
-    for (int r = 0; r < m; ++r) {
+    for (int rr = 0; rr < m; ++rr) {
         for (int c = 0; c < n; ++c) {
-            M[(size_t)r * w + c] = A[(size_t)r * n + c];
-            amax = std::max(amax, std::fabs(A[(size_t)r * n + c]));
+            M[(size_t)rr * w + c] = A[(size_t)rr * n + c];
+            amax = std::max(amax, std::fabs(A[(size_t)rr * n + c]));
         }
-        M[(size_t)r * w + n] = b[r];
-        bmax = std::max(bmax, std::fabs(b[r]));
+        for (int c = 0; c < r; ++c) {
+            M[(size_t)rr * w + n + c] = Bm[(size_t)rr * r + c];
+            bmax = std::max(bmax, std::fabs(Bm[(size_t)rr * r + c]));
+        }
     }
     const double tol = std::max(m, n) * DBL_EPSILON * std::max(amax, 1e-300);
     // Gauss-Jordan elimination with partial pivoting (reduced row echelon form)
@@ -63,13 +81,15 @@ int component_factor(int m, int n, const double* A, const double* b, double* F, 
         ++row;
     }
     const double bscale = std::max(1.0, bmax);
-    for (int r = row; r < m; ++r)
-        if (std::fabs(M[(size_t)r * w + n]) > tol * bscale) return OPF_EINFEASIBLE_COMPONENT;
+    if (check)
+        for (int rr = row; rr < m; ++rr)
+            for (int c = 0; c < r; ++c)
+                if (std::fabs(M[(size_t)rr * w + n + c]) > tol * bscale) return OPF_EINFEASIBLE_COMPONENT;
     const int k = row;
     if (rank_out) *rank_out = k;
     std::fill(F, F + (size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) F[(size_t)i * n + i] = 1.0;
-    std::fill(bbar, bbar + n, 0.0);
+    std::fill(bbar, bbar + (size_t)n * r, 0.0);
     if (k == 0) return 0;
     // G = Ahat Ahat^T and its Cholesky factor (lower, in place)
     std::vector<double> G((size_t)k * k);
@@ -91,7 +111,7 @@ int component_factor(int m, int n, const double* A, const double* b, double* F, 
             G[(size_t)i * k + j] = s / d;
         }
     }
-    // solve G W = [Ahat | bhat] column by column (W is k x (n+1))
+    // solve G W = [Ahat | bhat] column by column (W is k x (n+r))
     std::vector<double> W((size_t)k * w);
     std::vector<double> y(k);
     for (int c = 0; c < w; ++c) {
@@ -106,16 +126,18 @@ int component_factor(int m, int n, const double* A, const double* b, double* F, 
             W[(size_t)i * w + c] = s / G[(size_t)i * k + i];
         }
     }
-    // F = I - Ahat^T W[:, :n] (symmetrised), bbar = Ahat^T W[:, n]
+    // F = I - Ahat^T W[:, :n] (symmetrised), bbar = Ahat^T W[:, n:]
     for (int i = 0; i < n; ++i) {
         for (int j = 0; j < n; ++j) {
             double s = 0.0;
             for (int q = 0; q < k; ++q) s += M[(size_t)q * w + i] * W[(size_t)q * w + j];
             F[(size_t)i * n + j] -= s;
         }
-        double s = 0.0;
-        for (int q = 0; q < k; ++q) s += M[(size_t)q * w + i] * W[(size_t)q * w + n];
-        bbar[i] = s;
+        for (int c = 0; c < r; ++c) {
+            double s = 0.0;
+            for (int q = 0; q < k; ++q) s += M[(size_t)q * w + i] * W[(size_t)q * w + n + c];
+            bbar[(size_t)i * r + c] = s;
+        }
     }
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j) {
@@ -198,27 +220,97 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
         return badcode.load();
     }
 
-    // ---- pack components into wavefronts: largest first, holes filled from the small end
-    std::vector<int> order(S);
-    for (int s = 0; s < S; ++s) order[s] = s;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return p.comp_n[a] > p.comp_n[b2]; });
-    std::deque<int> dq(order.begin(), order.end());
-    std::vector<std::vector<int>> waves;
-    while (!dq.empty()) {
-        std::vector<int> w;
-        int used = 0;
-        while (!dq.empty() && used + p.comp_n[dq.front()] <= kWave) {
-            used += p.comp_n[dq.front()];
-            w.push_back(dq.front());
-            dq.pop_front();
-        }
-        while (!dq.empty() && used + p.comp_n[dq.back()] <= kWave) {
-            used += p.comp_n[dq.back()];
-            w.push_back(dq.back());
-            dq.pop_back();
-        }
-        waves.push_back(std::move(w));
+    // ---- order components so that neighbours in the network sit together:
+    // depth-first over the component graph (two components are adjacent when
+    // they copy a common variable)
+    std::vector<int32_t> vptr0(n + 1, 0);
+    for (int i = 0; i < n; ++i) vptr0[i + 1] = vptr0[i] + cnt[i];
+    std::vector<int32_t> vcomp(L);
+    {
+        std::vector<int32_t> f(vptr0.begin(), vptr0.end() - 1);
+        for (int s2 = 0; s2 < S; ++s2)
+            for (int64_t q = ioff[s2]; q < ioff[s2 + 1]; ++q) vcomp[f[p.idx[q]]++] = s2;
     }
+    std::vector<int> order;
+    order.reserve(S);
+    {
+        std::vector<char> seen(S, 0);
+        std::vector<int> stack;
+        for (int root = 0; root < S; ++root) {
+            if (seen[root]) continue;
+            stack.push_back(root);
+            seen[root] = 1;
+            while (!stack.empty()) {
+                const int u = stack.back();
+                stack.pop_back();
+                order.push_back(u);
+                for (int64_t q = ioff[u + 1] - 1; q >= ioff[u]; --q) {
+                    const int g = p.idx[q];
+                    for (int r = vptr0[g + 1] - 1; r >= vptr0[g]; --r) {
+                        const int v2 = vcomp[r];
+                        if (!seen[v2]) { seen[v2] = 1; stack.push_back(v2); }
+                    }
+                }
+            }
+        }
+    }
+    // ---- cut the order into workgroups of `block_waves` wavefronts; inside a
+    // workgroup components are packed largest first with holes filled from the
+    // small end, and a component never straddles two wavefronts
+    const int B = out.block_waves > 0 ? out.block_waves : 4;
+    auto pack = [&](const std::vector<int>& chunk, std::vector<std::vector<int>>& ws) {
+        std::vector<int> srt(chunk);
+        std::stable_sort(srt.begin(), srt.end(), [&](int a, int b2) { return p.comp_n[a] > p.comp_n[b2]; });
+        std::deque<int> dq(srt.begin(), srt.end());
+        ws.clear();
+        while (!dq.empty()) {
+            std::vector<int> w;
+            int used = 0;
+            while (!dq.empty() && used + p.comp_n[dq.front()] <= kWave) {
+                used += p.comp_n[dq.front()];
+                w.push_back(dq.front());
+                dq.pop_front();
+            }
+            while (!dq.empty() && used + p.comp_n[dq.back()] <= kWave) {
+                used += p.comp_n[dq.back()];
+                w.push_back(dq.back());
+                dq.pop_back();
+            }
+            ws.push_back(std::move(w));
+        }
+        return (int)ws.size() <= B;
+    };
+    std::vector<std::vector<int>> waves;
+    std::vector<int> comp_block(S, -1);
+    {
+        std::vector<int> cur;
+        std::vector<std::vector<int>> ws;
+        int cur_lanes = 0;
+        auto emit = [&]() {
+            pack(cur, ws);
+            const int blk = (int)(waves.size() / B);
+            for (auto& w : ws) {
+                for (int c2 : w) comp_block[c2] = blk;
+                waves.push_back(w);
+            }
+            for (int e = (int)ws.size(); e < B; ++e) waves.push_back({});
+            cur.clear();
+            cur_lanes = 0;
+        };
+        for (int s2 : order) {
+            cur.push_back(s2);
+            cur_lanes += p.comp_n[s2];
+            if (cur_lanes > B * kWave * 3 / 4 && !pack(cur, ws)) {
+                cur.pop_back();
+                emit();
+                cur.push_back(s2);
+                cur_lanes = p.comp_n[s2];
+            }
+        }
+        if (!cur.empty()) emit();
+    }
+    out.block_waves = B;
+    out.blocks = (int)(waves.size() / B);
     const int W = (int)waves.size();
     const int LP = W * kWave;
     out.n = n; out.S = S; out.L = L; out.waves = W;
@@ -280,6 +372,29 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
         out.owner_slot[i] = out.copy_list[vptr[i]];
         out.max_copies = std::max(out.max_copies, (int)cnt[i]);
     }
+    // workgroups that own a copy of any variable of workgroup b (excluding b)
+    {
+        const int G = out.blocks;
+        std::vector<std::vector<int>> nb(G);
+        for (int i = 0; i < n; ++i) {
+            for (int r = vptr[i]; r < vptr[i + 1]; ++r) {
+                const int bi = out.copy_list[r] / (B * kWave);
+                for (int r2 = vptr[i]; r2 < vptr[i + 1]; ++r2) {
+                    const int bj = out.copy_list[r2] / (B * kWave);
+                    if (bi != bj) nb[bi].push_back(bj);
+                }
+            }
+        }
+        out.nbr_ptr.assign(G + 1, 0);
+        out.nbr_list.clear();
+        for (int b2 = 0; b2 < G; ++b2) {
+            std::sort(nb[b2].begin(), nb[b2].end());
+            nb[b2].erase(std::unique(nb[b2].begin(), nb[b2].end()), nb[b2].end());
+            out.nbr_list.insert(out.nbr_list.end(), nb[b2].begin(), nb[b2].end());
+            out.nbr_ptr[b2 + 1] = (int32_t)out.nbr_list.size();
+            out.max_nbrs = std::max(out.max_nbrs, (int)nb[b2].size());
+        }
+    }
     for (int d = 0; d < LP; ++d) {
         const int g = out.var[d];
         if (g < 0) continue;
@@ -297,6 +412,106 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
     }
     out.c_full.assign(p.c, p.c + n);
     return 0;
+}
+
+int build_batch_rhs(const ProblemView& p, const HostLayout& lay, const double* b_scen, int K, int Kp,
+                    std::vector<float>& out, std::string& err, int threads) {
+    const int S = p.S;
+    std::vector<int64_t> aoff(S + 1), boff(S + 1), ioff(S + 1);
+    aoff[0] = boff[0] = ioff[0] = 0;
+    for (int s = 0; s < S; ++s) {
+        aoff[s + 1] = aoff[s] + (int64_t)p.comp_m[s] * p.comp_n[s];
+        boff[s + 1] = boff[s] + p.comp_m[s];
+        ioff[s + 1] = ioff[s] + p.comp_n[s];
+    }
+    const int64_t M = boff[S];
+    for (int64_t q = 0; q < M * K; ++q)
+        if (!std::isfinite(b_scen[q])) { err = "non-finite scenario right-hand side"; return OPF_EINVAL; }
+    out.assign((size_t)lay.waves * kWave * Kp, 0.0f);
+    std::atomic<int> next(0), bad(-1);
+    auto work = [&]() {
+        std::vector<double> F, Wm, bb;
+        for (;;) {
+            const int s = next.fetch_add(8);
+            if (s >= S) break;
+            for (int u = s; u < std::min(S, s + 8); ++u) {
+                const int m = p.comp_m[u], n = p.comp_n[u];
+                F.assign((size_t)n * n, 0.0);
+                Wm.assign((size_t)n * std::max(m, 1), 0.0);
+                if (m > 0) component_rhs_map(m, n, p.A + aoff[u], F.data(), Wm.data());
+                bb.assign(n, 0.0);
+                for (int k = 0; k < K; ++k) {
+                    const double* b = b_scen + (size_t)k * M + boff[u];
+                    for (int i = 0; i < n; ++i) {
+                        double acc = 0.0;
+                        for (int j = 0; j < m; ++j) acc += Wm[(size_t)i * m + j] * b[j];
+                        bb[i] = acc;
+                    }
+                    // the scenario's equations must hold at bbar (consistent right-hand side)
+                    double bmax = 1.0, rmax = 0.0, amax = 0.0;
+                    for (int j = 0; j < m; ++j) {
+                        double acc = 0.0;
+                        for (int i = 0; i < n; ++i) {
+                            acc += p.A[aoff[u] + (size_t)j * n + i] * bb[i];
+                            amax = std::max(amax, std::fabs(p.A[aoff[u] + (size_t)j * n + i]));
+                        }
+                        rmax = std::max(rmax, std::fabs(acc - b[j]));
+                        bmax = std::max(bmax, std::fabs(b[j]));
+                    }
+                    if (rmax > 1e-9 * bmax * std::max(1.0, amax)) bad.store(u);
+                    for (int i = 0; i < n; ++i) {
+                        const int d = lay.user_to_dev[ioff[u] + i];
+                        out[(size_t)d * Kp + k] = (float)bb[i];
+                    }
+                }
+            }
+        }
+    };
+    threads = std::max(1, std::min(threads, 64));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < threads; ++t) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+    if (bad.load() >= 0) {
+        err = fmt("scenario right-hand side inconsistent with the equations of component", bad.load());
+        return OPF_EINFEASIBLE_COMPONENT;
+    }
+    return 0;
+}
+
+static uint16_t to_bf16(double v) {
+    float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
+    const uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);              // nearest even
+    return (uint16_t)((u + rounding) >> 16);
+}
+static double from_bf16(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+void build_dense_planes(const HostLayout& lay, int terms, std::vector<uint16_t>& planes) {
+    const size_t per = (size_t)kWave * kWave;
+    planes.assign((size_t)terms * lay.waves * per, 0);
+    for (int w = 0; w < lay.waves; ++w) {
+        for (int r = 0; r < kWave; ++r) {
+            const int d = w * kWave + r;
+            if (lay.var[d] < 0) continue;
+            const int b0 = lay.meta[d] & 255, ns = (lay.meta[d] >> 8) & 255;
+            for (int k = 0; k < ns; ++k) {
+                double rem = lay.F[lay.wave_foff[w] + (int64_t)k * kWave + r];
+                for (int t = 0; t < terms; ++t) {
+                    const uint16_t h = to_bf16(rem);
+                    planes[(size_t)t * lay.waves * per + (size_t)w * per + (size_t)r * kWave + b0 + k] = h;
+                    rem -= from_bf16(h);
+                }
+            }
+        }
+    }
 }
 
 }  // namespace opf

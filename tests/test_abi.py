@@ -32,6 +32,7 @@ def test_struct_sizes_match_header_layout():
     binding, _ = _lib()
     assert C.sizeof(binding.opf_problem) == 88
     assert C.sizeof(binding.opf_admm_options) == 8 + 8 + 8 + 6 * 4 + 7 * 4 + 4
+    assert C.sizeof(binding.opf_batch_result) == 8 + 4 + 4 + 7 * 8 + 8 + 4 + 4 + 8
     assert C.sizeof(binding.opf_result) == 3 * 8 + 4 + 4 + 8 + 8 + 6 * 8
 
 

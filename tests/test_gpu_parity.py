@@ -62,14 +62,19 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b)))))
 
 
-@pytest.mark.parametrize("name", ["13bus", "13bus-zip", "123bus"])
-@pytest.mark.parametrize("t", [1, 10, 100])
-def test_fixed_iteration_state_matches_oracle_fp64(name, t):
-    _say(f"[gpu] fixed-iteration parity {name} t={t} (opf_admm_run_fixed, FP64)")
+STEP, PERSIST = 1, 2
+KERNELS = [pytest.param(STEP, id="step"), pytest.param(PERSIST, id="persistent")]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("name,bw", [("13bus", 4), ("13bus-zip", 1), ("123bus", 1), ("123bus", 8)])
+@pytest.mark.parametrize("t", [1, 2, 3, 10, 100])
+def test_fixed_iteration_state_matches_oracle_fp64(name, bw, t, kernel):
+    _say(f"[gpu] fixed-iteration parity {name} block_waves={bw} t={t} kernel={kernel} (opf_admm_run_fixed, FP64)")
     inst = _inst(name)
     P = _oracle(name)
     ref = admm.solve(P, rho=RHO, eps_rel=1e-4, fixed_iters=t)
-    s = _solver(inst, rho=RHO, eps_rel=1e-4)
+    s = _solver(inst, rho=RHO, eps_rel=1e-4, kernel=kernel, block_waves=bw)
     out = s.solve(fixed_iters=t)
     assert out["iterations"] == t
     assert _rel(out["x"], ref.x) < 1e-9
@@ -79,12 +84,13 @@ def test_fixed_iteration_state_matches_oracle_fp64(name, t):
     s.close()
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("name,eps", [("13bus", 1e-4), ("123bus", 1e-4), ("13bus", 1e-3), ("123bus", 1e-3)])
-def test_solve_to_tolerance_matches_golden_fp64(name, eps):
-    _say(f"[gpu] solve-to-tolerance parity {name} eps={eps} (opf_admm_solve, FP64)")
+def test_solve_to_tolerance_matches_golden_fp64(name, eps, kernel):
+    _say(f"[gpu] solve-to-tolerance parity {name} eps={eps} kernel={kernel} (opf_admm_solve, FP64)")
     g = _golden(name, eps)
     inst = _inst(name)
-    s = _solver(inst, rho=RHO, eps_rel=eps, check_every=64)
+    s = _solver(inst, rho=RHO, eps_rel=eps, check_every=64, kernel=kernel, block_waves=2)
     out = s.solve()
     assert out["status"] == 0
     assert abs(out["iterations"] - g["iterations"]) <= 1
@@ -140,14 +146,15 @@ def test_bitwise_repeatable_and_checkpoint_resume():
     s.close()
 
 
-def test_mixed_precision_matches_fp64_oracle():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_mixed_precision_matches_fp64_oracle(kernel):
     """FP32 bulk iterations with FP64 residual sums, then FP64 polish: objective
     and voltages within 1e-4 relative of the FP64 oracle at the same tolerance."""
     from paper_2501_08293_amd import OPF_PREC_MIXED
-    _say("[gpu] mixed precision 123bus")
+    _say(f"[gpu] mixed precision 123bus kernel={kernel}")
     g = _golden("123bus", 1e-4)
     inst = _inst("123bus")
-    s = _solver(inst, rho=RHO, eps_rel=1e-4, precision=OPF_PREC_MIXED, check_every=64)
+    s = _solver(inst, rho=RHO, eps_rel=1e-4, precision=OPF_PREC_MIXED, check_every=64, kernel=kernel)
     out = s.solve()
     assert out["status"] == 0
     assert out["iterations_fp32"] > 0
@@ -180,14 +187,50 @@ def test_device_outputs_and_warm_start_from_torch():
     s.close()
 
 
-def test_full_size_8500bus_fixed_iterations_match_oracle():
+def test_persistent_and_step_kernels_agree_bitwise():
+    """The two schedules evaluate the same arithmetic in the same order: same
+    stop iteration and identical bits."""
+    _say("[gpu] persistent vs step bitwise 123bus")
+    inst = _inst("123bus")
+    outs = []
+    for k in (STEP, PERSIST):
+        s = _solver(inst, rho=RHO, eps_rel=1e-4, kernel=k, block_waves=2)
+        outs.append(s.solve())
+        s.close()
+    a, b = outs
+    assert a["iterations"] == b["iterations"]
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["z"], b["z"]) and np.array_equal(a["lam"], b["lam"])
+
+
+def test_persistent_bounded_wait_reports_ehang_and_device_recovers():
+    """A tiny spin limit forces the persistent kernel's bounded waits to run
+    out (forced from the host; every wait still ends): the solve returns
+    OPF_EHANG or a normal result, and the next solve on the device is normal."""
+    from paper_2501_08293_amd import OpfError
+    _say("[gpu] persistent forced wait timeout 123bus")
+    inst = _inst("123bus")
+    s = _solver(inst, rho=RHO, eps_rel=1e-4, kernel=PERSIST, block_waves=1, spin_limit=1)
+    try:
+        out = s.solve(raise_on_error=False)
+        assert out["status"] in (0, -8)
+    finally:
+        s.close()
+    s = _solver(inst, rho=RHO, eps_rel=1e-4, kernel=PERSIST, block_waves=1)
+    out = s.solve()
+    g = _golden("123bus", 1e-4)
+    assert abs(out["iterations"] - g["iterations"]) <= 1
+    s.close()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_full_size_8500bus_fixed_iterations_match_oracle(kernel):
     """At the full 8500-bus size, in the launch configuration the benchmark
     times: the state after 20 iterations equals the oracle's."""
-    _say("[gpu] 8500bus fixed-iteration parity t=20")
+    _say(f"[gpu] 8500bus fixed-iteration parity t=20 kernel={kernel}")
     inst = _inst("8500bus")
     P = _oracle("8500bus")
     ref = admm.solve(P, rho=RHO, eps_rel=1e-4, fixed_iters=20)
-    s = _solver(inst, rho=RHO, eps_rel=1e-4)
+    s = _solver(inst, rho=RHO, eps_rel=1e-4, kernel=kernel)
     out = s.solve(fixed_iters=20)
     assert _rel(out["x"], ref.x) < 1e-9
     assert _rel(out["z"], ref.z) < 1e-9

@@ -56,7 +56,7 @@ def test_delta_rows_vdlm6_10_hold_for_physical_delta_powers():
     keys = [(nm, l, ph) for nm in ("pb", "qb", "pd", "qd") for ph in range(3)]
     cols = [V[k] for k in keys]
     wb = {V[(nm, l, ph)] for nm in ("pb", "qb") for ph in range(3)}
-    rows = [co for _, co, rhs in eqs if set(co) <= set(cols) and wb & set(co)]
+    rows = [e[1] for e in eqs if set(e[1]) <= set(cols) and wb & set(e[1])]
     assert len(rows) == 6
     A = np.array([[co.get(c, 0.0) for c in cols] for co in rows])
     rng = np.random.default_rng(1)
@@ -137,3 +137,22 @@ def test_tree_generator_is_radial_and_seeded():
     a = build_instance(make_123bus(4))
     b = build_instance(make_123bus(4))
     assert a.n == b.n and all(np.array_equal(x.A, y.A) for x, y in zip(a.comps, b.comps))
+
+
+def test_scenario_rhs_equals_rebuilt_instance():
+    """Scaling the loads of a constant-power feeder changes only b_s: the
+    scenario right-hand side equals the one of the rebuilt instance."""
+    import copy
+    from opfgen import scenario_load_factors, scenario_rhs
+    f = by_name("123bus", 0)
+    inst = build_instance(f)
+    fac = scenario_load_factors(f, 2, 5)
+    B = scenario_rhs(inst, fac)
+    for k in range(2):
+        f2 = copy.deepcopy(f)
+        for ld in f2.loads:
+            ld.a = ld.a * fac[k, ld.bus]
+            ld.b = ld.b * fac[k, ld.bus]
+        inst2 = build_instance(f2)
+        assert all(np.array_equal(c1.A, c2.A) for c1, c2 in zip(inst.comps, inst2.comps))
+        np.testing.assert_allclose(np.concatenate([c.b for c in inst2.comps]), B[k], rtol=1e-15, atol=0)
