@@ -1,16 +1,23 @@
 """Benchmark of the solver-free componentwise ADMM on one MI355X.
 
-A step is one complete solve (Algorithm 1 from the default start point until
-the relative residual test holds at eps_rel = 1e-4, rho = 100) of the seeded
-synthetic 8500-bus feeder, with the problem already resident in HBM (set-up is
-done and timed separately).  `value` is ADMM iterations per second over the
-timed steps; `ms_per_step` is the time to tolerance.
+Headline (`value`): the synthetic 8500-bus feeder, solved from the default
+start point until the paper's relative residual test holds at eps_rel = 1e-4
+(rho = 100), with the problem resident in HBM (set-up done and timed
+separately).  A step is one complete solve; `value` is ADMM iterations per
+second over the timed steps and `ms_per_step` is the time to tolerance.
 
-    python bench.py [--steps K] [--warmup W] [--workload 8500bus] [--precision mixed|fp64]
+Also reported on the same JSON line:
+  * roofline of the dominant kernel (the FP32 persistent iteration kernel),
+  * the FP64 CPU oracle on a bounded sample of the same workload,
+  * batch: 256 load scenarios of a 2500-bus feeder on the MFMA path,
+  * serving: a Poisson stream of mixed-size, reconfigured feeders through the
+    serving runtime, against the same stream served one solve at a time.
+
+    python bench.py [--steps K] [--warmup W] [--skip-batch] [--skip-serve]
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -19,40 +26,59 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_DENSE_PEAK_TFLOPS = 2500.0
 METRIC = "8500-bus ADMM iters/s & time-to-1e-4 residual; served solves/s + p99 latency"
+KERNEL_SOURCES = ["paper_2501_08293_amd/csrc/admm_persistent.hip", "paper_2501_08293_amd/csrc/admm_kernels.h"]
 
 
 def algorithmic_bytes_per_iteration(sum_ns2, L, n, elem):
-    """Minimum bytes one iteration must move without re-use tricks: the
-    factors (elem * sum n_s^2), per slot bbar, index, lambda and z read+write
-    and the consensus gathers ((7 elem + 8) L), per variable the x gather and
-    write, bounds and row pointer ((4 elem + 4) n)."""
+    """Minimum bytes one iteration must move without re-using data across
+    iterations: the factors (elem * sum n_s^2), per slot bbar, index, lambda
+    and z read+write and the consensus gathers ((7 elem + 8) L), per variable
+    the x gather and write, bounds and row pointer ((4 elem + 4) n)."""
     return elem * sum_ns2 + (7 * elem + 8) * L + (4 * elem + 4) * n
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="8500bus")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--eps", type=float, default=1e-4)
-    ap.add_argument("--check-every", type=int, default=1024)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel", default="auto", choices=["auto", "step", "persistent"])
     ap.add_argument("--block-waves", type=int, default=0)
+    ap.add_argument("--check-every", type=int, default=1024)
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="time this many iterations per step instead of solving to tolerance")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--batch-workload", default="2500bus")
+    ap.add_argument("--batch-k", type=int, default=256)
+    ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--serve-families", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-eps", type=float, default=1e-3)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device copy of known size (counter calibration for profiles)")
     return ap.parse_args()
 
 
 def cpu_baseline(inst, eps, budget_s):
     """The FP64 oracle timed on the host on a bounded sample of the same
     workload: as many iterations of Algorithm 1 as fit in about budget_s."""
-    import numpy as np
     from oracle import admm
     P = admm.setup(inst)
     t0 = time.perf_counter()
@@ -66,30 +92,50 @@ def cpu_baseline(inst, eps, budget_s):
         aff = len(os.sched_getaffinity(0))
     except Exception:
         aff = os.cpu_count()
-    return {"value": iters / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} FP64 iterations of the same {inst.name} instance from the default start "
-                      f"({dt:.1f} s, NumPy single thread; host affinity {aff} cores)"}
+    return {"value": round(iters / dt, 2), "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} FP64 iterations of Algorithm 1 on the same {inst.name} instance from the default "
+                      f"start ({dt:.1f} s, NumPy on one thread; host affinity {aff} cores)"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-    import numpy as np
+def copy_calibration():
+    """A plain device copy of 256 MiB (reads 256 MiB, writes 256 MiB): the
+    reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
     import torch
+    n = 256 * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
+
+
+def traffic_from_profiles(workload, precision):
+    """HBM bytes per iteration from committed counter runs, if they were
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_admm_persistent_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d
+
+
+def single_instance(args, torch):
     from opfgen import build_instance, by_name
     from paper_2501_08293_amd import OPF_PREC_FP64, OPF_PREC_MIXED, Solver
-
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(0)
     t0 = time.perf_counter()
     inst = build_instance(by_name(args.workload, args.seed))
     gen_s = time.perf_counter() - t0
     stream = torch.cuda.Stream()
     prec = OPF_PREC_MIXED if args.precision == "mixed" else OPF_PREC_FP64
-    flat = (inst.n, inst.c, inst.lb, inst.ub, inst.var_kind) + tuple(inst.flat())
     kern = {"auto": 0, "step": 1, "persistent": 2}[args.kernel]
+    flat = (inst.n, inst.c, inst.lb, inst.ub, inst.var_kind) + tuple(inst.flat())
     solver = Solver(*flat, rho=100.0, eps_rel=args.eps, precision=prec, check_every=args.check_every,
                     kernel=kern, block_waves=args.block_waves, stream=stream.cuda_stream)
     info = solver.info()
@@ -98,31 +144,37 @@ def main():
     for _ in range(args.warmup):
         solver.solve(x=x, fixed_iters=fixed)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     results = []
-    torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        r = solver.solve(x=x, fixed_iters=fixed)
-        ev[k][1].record(stream)
-        results.append(r)
+    for _ in range(args.steps):
+        results.append(solver.solve(x=x, fixed_iters=fixed))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    dev_ms = sum(a.elapsed_time(b) for a, b in ev)
+    solver.close()
     iters = sum(r["iterations"] for r in results)
     it32 = sum(r["iterations_fp32"] for r in results)
     it64 = iters - it32
-    value = iters / wall
-    # dominant kernel: the fused iteration (FP32 bulk in mixed mode)
-    elem = 4 if prec == OPF_PREC_MIXED else 8
+    k32 = sum(r["kernel_ms_fp32"] for r in results)
+    k64 = sum(r["kernel_ms"] for r in results) - k32
     bpi32 = algorithmic_bytes_per_iteration(info.sum_ns2, inst.L, inst.n, 4)
     bpi64 = algorithmic_bytes_per_iteration(info.sum_ns2, inst.L, inst.n, 8)
-    alg_bytes = bpi32 * it32 + bpi64 * it64
-    achieved = alg_bytes / (dev_ms * 1e-3) / 1e9
+    # dominant kernel: the FP32 bulk in mixed mode, FP64 otherwise
+    if prec == OPF_PREC_MIXED and it32 > 0:
+        dom_name, dom_bytes, dom_ms, dom_iters = "admm_persistent_kernel<float, 4>", bpi32, k32, it32
+    else:
+        dom_name, dom_bytes, dom_ms, dom_iters = "admm_persistent_kernel<double, 4>", bpi64, k64, it64
+    dom_launches = args.steps
+    if info.kernel != 2:
+        dom_name = dom_name.replace("persistent", "step")
+        dom_launches = dom_iters
+    achieved = dom_bytes * dom_iters / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    tr = traffic_from_profiles(args.workload, args.precision)
+    traffic = None
+    if tr is not None:
+        traffic = round(tr["bytes_per_iteration"] * dom_iters / max(dom_launches, 1))
     line = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": round(iters / wall, 1),
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -140,6 +192,7 @@ def main():
             "iterations_per_solve": results[-1]["iterations"],
             "iterations_fp32_per_solve": results[-1]["iterations_fp32"],
             "time_to_tolerance_ms": round(1e3 * wall / args.steps, 3),
+            "status": results[-1]["status"],
             "objective": results[-1]["objective"],
             "setup_ms": round(info.setup_ms, 1),
             "generator_s": round(gen_s, 2),
@@ -148,6 +201,8 @@ def main():
             "kernel": {1: "step", 2: "persistent"}.get(info.kernel, "?"),
             "block_waves": info.block_waves,
             "workgroups": info.grid_blocks,
+            "factors_in_lds": info.factors_in_lds,
+            "kernel_ms_per_solve": round(sum(r["kernel_ms"] for r in results) / args.steps, 3),
         },
         "roofline": {
             "bound": "hbm",
@@ -155,16 +210,158 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "kernel": "admm_step_kernel (fused global+local+dual+residual iteration)",
-            "bytes_per_iteration_fp32": bpi32,
-            "bytes_per_iteration_fp64": bpi64,
-            "avg_iteration_us": round(1e3 * dev_ms / iters, 3),
+            "traffic": traffic,
+            "kernel": dom_name,
+            "bytes_per_iteration": dom_bytes,
+            "avg_launch_ms": round(dom_ms / max(dom_launches, 1), 4),
+            "avg_iteration_us": round(1e3 * dom_ms / max(dom_iters, 1), 3),
+            "kernel_source_hash": kernel_source_hash(),
         },
     }
+    return line, inst
+
+
+def batch_leg(args, torch):
+    import numpy as np
+    from opfgen import build_instance, by_name, scenario_load_factors, scenario_rhs
+    from paper_2501_08293_amd import BatchSolver
+    f = by_name(args.batch_workload, args.seed)
+    inst = build_instance(f)
+    K = args.batch_k
+    B = scenario_rhs(inst, scenario_load_factors(f, K, seed=1000))
+    st = torch.cuda.Stream()
+    s = BatchSolver(inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, *inst.flat(), b_scen=B, rho=100.0,
+                    eps_rel=args.eps, check_every=256, stream=st.cuda_stream)
+    info = s.info()
+    t0 = time.perf_counter()
+    out = s.solve()
+    wall = time.perf_counter() - t0
+    s.close()
+    it = out["iterations"]
+    T = int(out["total_iterations"])
+    # MFMA work issued per batch iteration: per packed wavefront and 64-scenario
+    # chunk, 4 tiles x 4 k-steps x 6 products of 32x32x16
+    chunks = (K + 63) // 64
+    mfma_flops = info.waves * chunks * 4 * 4 * 6 * (2 * 32 * 32 * 16) * T
+    useful_flops = 2 * info.sum_ns2 * int(it.sum())
+    tf = mfma_flops / wall / 1e12
+    return {
+        "workload": f"{inst.name}: {K} load scenarios (lognormal(0, 0.3) per bus), shared A_s; eps_rel={args.eps:g}",
+        "scenarios": K, "converged": int(out["converged"]), "status": int(out["status"]),
+        "time_to_all_ms": round(1e3 * wall, 1), "batch_iterations": T,
+        "scenario_iterations_min_med_max": [int(it.min()), int(np.median(it)), int(it.max())],
+        "scenario_solves_per_s": round(K / wall, 2),
+        "scenario_iterations_per_s": round(float(it.sum()) / wall, 1),
+        "us_per_batch_iteration": round(1e6 * wall / max(T, 1), 2),
+        "mfma": {"issued_tflops": round(tf, 2), "peak_tflops_bf16_dense": BF16_DENSE_PEAK_TFLOPS,
+                 "frac": round(tf / BF16_DENSE_PEAK_TFLOPS, 5),
+                 "useful_fraction_of_issued": round(useful_flops * 6 / max(mfma_flops, 1), 4)},
+        "precision": "bf16 three-term split products on MFMA, fp32 accumulate, fp32 state, fp64 residual sums",
+    }
+
+
+def serve_leg(args, torch):
+    import numpy as np
+    from opfgen import build_instance, scenario_rhs
+    from opfgen.serving import component_keys, make_family, poisson_arrivals, reconfigure
+    from paper_2501_08293_amd import Server, Solver
+    t0 = time.perf_counter()
+    pool = []          # (family id, instance, component keys)
+    for fid in range(args.serve_families):
+        fam = make_family(fid, args.seed)
+        rng = np.random.default_rng([args.seed, fid, 5])
+        variants = [fam.base] + [reconfigure(fam, k, rng) for k in range(min(2, len(fam.ties)))]
+        for g in variants:
+            inst = build_instance(g)
+            pool.append((fid, inst, component_keys(inst)))
+    gen_s = time.perf_counter() - t0
+    N = args.serve_requests
+    rng = np.random.default_rng([args.seed, 808])
+    arrivals = poisson_arrivals(N, args.serve_rate, args.seed)
+    reqs = []
+    for k in range(N):
+        fid, inst, keys = pool[int(rng.integers(len(pool)))]
+        fac = np.clip(rng.lognormal(0.0, 0.3, size=(1, inst.feeder.n_bus)), 0.5, 1.0)
+        b = scenario_rhs(inst, fac)[0]
+        cm, cn, A, _, idx = inst.flat()
+        reqs.append((fid, inst, keys, (inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, cm, cn, A, b, idx)))
+    # continuous batching through the serving runtime
+    st = torch.cuda.Stream()
+    srv = Server(rho=100.0, eps_rel=args.serve_eps, iters_per_poll=32, arena_bytes=8 << 30,
+                 max_workgroups=16384, setup_threads=6, stream=st.cuda_stream)
+    done = {}
+    ids = {}
+    t_start = time.perf_counter()
+    k = 0
+    while len(done) < N:
+        now = time.perf_counter() - t_start
+        while k < N and arrivals[k] <= now:
+            fid, inst, keys, arrs = reqs[k]
+            ids[srv.submit(*arrs, family=fid, comp_keys=keys)] = k
+            k += 1
+        for r in srv.poll(max_out=256, wait_ms=1):
+            done[ids[r["request_id"]]] = r
+    span = time.perf_counter() - t_start
+    sstats = srv.stats()
+    srv.close()
+    lat = np.array([done[i]["latency_ms"] for i in range(N)])
+    ok = sum(1 for i in range(N) if done[i]["status"] == 0)
+    warm = sum(1 for i in range(N) if done[i]["warm_components"] > 0)
+    # baseline: the same trace served one solve at a time, FIFO, cold start,
+    # with the single-instance solver (set-up included, as in the runtime)
+    base_lat = []
+    base_ok = 0
+    free_at = 0.0
+    base_obj_err = []
+    t_b = time.perf_counter()
+    for i in range(N):
+        start = max(arrivals[i], free_at)
+        wait = start - (time.perf_counter() - t_b)
+        if wait > 0:
+            time.sleep(wait)
+        fid, inst, keys, arrs = reqs[i]
+        s = Solver(*arrs, rho=100.0, eps_rel=args.serve_eps, check_every=256, stream=st.cuda_stream)
+        r = s.solve()
+        s.close()
+        base_ok += int(r["status"] == 0)
+        free_at = time.perf_counter() - t_b
+        base_lat.append(1e3 * (free_at - arrivals[i]))
+        base_obj_err.append(abs(r["objective"] - done[i]["objective"]) / max(1e-12, abs(r["objective"])))
+    base_lat = np.array(base_lat)
+    return {
+        "workload": f"{N} requests, Poisson {args.serve_rate:g}/s, {args.serve_families} feeder families "
+                    f"(13-8500 buses log-uniform, tie-switch reconfigurations, fresh loads), eps_rel={args.serve_eps:g}",
+        "solves_per_s": round(ok / span, 2),
+        "p50_latency_ms": round(float(np.percentile(lat, 50)), 1),
+        "p99_latency_ms": round(float(np.percentile(lat, 99)), 1),
+        "converged": ok, "warm_started": warm,
+        "baseline_one_at_a_time": {"solves_per_s": round(base_ok / free_at, 2),
+                                   "p50_latency_ms": round(float(np.percentile(base_lat, 50)), 1),
+                                   "p99_latency_ms": round(float(np.percentile(base_lat, 99)), 1),
+                                   "converged": base_ok},
+        "speedup_solves_per_s": round((ok / span) / max(base_ok / free_at, 1e-9), 2),
+        "max_objective_rel_diff_vs_baseline": float(max(base_obj_err)),
+        "launches": int(sstats["launches"]), "generator_s": round(gen_s, 1),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    line, inst = single_instance(args, torch)
+    if not args.skip_batch:
+        line["batch"] = batch_leg(args, torch)
+    if not args.skip_serve:
+        line["serving"] = serve_leg(args, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, args.eps, args.cpu_seconds)
-    solver.close()
     print(json.dumps(line), flush=True)
 
 

@@ -112,7 +112,10 @@ typedef struct opf_admm_options {
     int32_t spin_limit;     /* PERSISTENT: polls before a device-side wait gives up with
                                OPF_EHANG (0 = default, several seconds) */
     int32_t split_terms;    /* batched path: bfloat16 terms per operand on MFMA, 2 or 3 (0 = 3) */
-    int32_t reserved[5];
+    int32_t autotune;       /* 1: with kernel AUTO and block_waves 0, time short runs of each
+                               schedule and workgroup shape on this problem and keep the fastest
+                               (decisions cached per problem shape for the process) */
+    int32_t reserved[4];
 } opf_admm_options;
 
 /* Optional warm start: z0 and lambda0 in user slot order (length L). */
@@ -138,6 +141,9 @@ typedef struct opf_result {
     double   objective;        /* c^T x */
     double   pres, dres, eps_prim, eps_dual;   /* termination quantities at the last iteration */
     double   solve_ms;         /* wall time of the solve on the host clock */
+    double   kernel_ms;        /* device time of the iteration kernels (HIP events on the handle's stream) */
+    double   kernel_ms_fp32;   /* MIXED: the part spent in the FP32 phase */
+    int64_t  kernel_launches;  /* iteration-kernel launches (persistent: one per precision phase) */
 } opf_result;
 
 typedef struct opf_residuals {
@@ -159,7 +165,8 @@ typedef struct opf_admm_info {
     int32_t kernel;            /* OPF_KERNEL_STEP or OPF_KERNEL_PERSISTENT, as selected */
     int32_t persistent_capacity;   /* co-resident workgroups the device can hold */
     int32_t max_neighbours;    /* largest number of workgroups one workgroup waits on */
-    int32_t reserved[5];
+    int32_t factors_in_lds;    /* persistent schedule: bit 0 FP32, bit 1 FP64 factors held in LDS */
+    int32_t reserved[4];
 } opf_admm_info;
 
 typedef struct opf_admm_handle opf_admm_handle;
@@ -253,6 +260,84 @@ int opf_admm_solve_batch(opf_admm_batch* h, opf_batch_result* r);
 int opf_admm_batch_info(const opf_admm_batch* h, opf_admm_info* info);
 void opf_admm_destroy_batch(opf_admm_batch* h);
 const char* opf_admm_batch_last_error(const opf_admm_batch* h);
+
+/*
+ * ---- Serving runtime ---------------------------------------------------------
+ *
+ * A request loop for many independent solves (feeders of different sizes and
+ * switched topologies) arriving over time.  Submitted problems are set up on
+ * host threads, admitted into a device arena while their memory footprint fits
+ * (admission by HBM footprint), and iterated together: one launch of the
+ * fused iteration kernel advances every resident solve by one iteration of
+ * Algorithm 1, each with its own iteration count and termination test, so a
+ * solve that arrives while others run joins the next launch (continuous
+ * batching) and a finished one leaves it.  After a solve finishes its
+ * (z, lambda) stay resident in HBM under its feeder family; a later request of
+ * the same family starts from them component by component (warm start),
+ * matching components by caller-supplied keys.  Precision is FP64; a solve
+ * returns the same bits alone and in any mix.
+ */
+typedef struct opf_server opf_server;
+
+typedef struct opf_server_options {
+    opf_admm_options admm;     /* rho, eps_rel, max_iter of every solve */
+    int64_t arena_bytes;       /* device memory for resident solves (admission budget) */
+    int64_t warm_bytes;        /* device memory for warm-start states (least recently used evicted) */
+    int32_t max_slots;         /* most solves resident at once */
+    int32_t max_workgroups;    /* grid of the shared launch (sum of resident workgroups) */
+    int32_t iters_per_poll;    /* iterations between host polls of the stop flags */
+    int32_t setup_threads;     /* host threads for row reduction / factors / packing */
+    int32_t warm_start;        /* 1: use resident states of the same family */
+    int32_t reserved[5];
+} opf_server_options;
+
+typedef struct opf_served {
+    int64_t request_id;
+    int32_t status;            /* OPF_OK, OPF_NOT_CONVERGED, OPF_ENUMERIC, or a set-up / admission error */
+    int32_t warm_components;   /* components started from a resident state */
+    int64_t iterations;
+    double  objective;
+    double  pres, dres, eps_prim, eps_dual;
+    double  queue_ms;          /* submit -> admitted to the device */
+    double  latency_ms;        /* submit -> result ready */
+    double* x;                 /* the x buffer given at submit, now filled */
+} opf_served;
+
+typedef struct opf_server_stats {
+    int64_t submitted, completed, rejected;
+    int32_t resident, queued;
+    int64_t arena_used, arena_bytes, warm_used;
+    int64_t launches;          /* shared iteration launches so far */
+    double  busy_ms;           /* device time of the shared launches (host clock) */
+} opf_server_stats;
+
+void opf_server_default_options(opf_server_options* o);
+
+/* Starts the runtime (worker and set-up threads).  All device work runs on
+   `hip_stream` (NULL: a private stream). */
+int opf_server_create(const opf_server_options* o, void* hip_stream, opf_server** out);
+
+/*
+ * Queues one solve.  The problem arrays are copied before the call returns.
+ * `family` groups requests whose states may warm-start each other;
+ * `comp_keys` (S values, nullable) identify components across requests of a
+ * family (a component warm-starts when its key and size match).  x_out (host,
+ * n doubles, caller-owned) must stay valid until the result is polled.
+ * Returns 0 and the request id, or OPF_EINVAL / OPF_ENOMEM (footprint larger
+ * than the arena).
+ */
+int opf_server_submit(opf_server* s, const opf_problem* p, uint64_t family, const uint64_t* comp_keys,
+                      double* x_out, int64_t* request_id);
+
+/* Moves up to max_out finished results into out (waiting up to wait_ms for
+   the first); returns how many were written. */
+int opf_server_poll(opf_server* s, opf_served* out, int max_out, int wait_ms);
+
+int opf_server_get_stats(const opf_server* s, opf_server_stats* st);
+
+/* Stops the runtime; unfinished requests are dropped. */
+void opf_server_destroy(opf_server* s);
+const char* opf_server_last_error(const opf_server* s);
 
 /* Frees the handle and its device memory.  NULL is ignored. */
 void opf_admm_destroy(opf_admm_handle* h);

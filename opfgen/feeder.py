@@ -274,11 +274,24 @@ def _sweep_w(f: Feeder, der_on: bool) -> np.ndarray:
                 inj_p[g.bus] -= g.pmax
     flow_p = inj_p.copy()
     flow_q = inj_q.copy()
-    for ln in reversed(f.lines):            # children after parents in `lines`
+    # lines in breadth-first order from the substation
+    kids = [[] for _ in range(n)]
+    for ln in f.lines:
+        kids[ln.parent].append(ln)
+    order = []
+    frontier = [0]
+    while frontier:
+        nxt = []
+        for a in frontier:
+            for ln in kids[a]:
+                order.append(ln)
+                nxt.append(ln.child)
+        frontier = nxt
+    for ln in reversed(order):
         flow_p[ln.parent] += flow_p[ln.child]
         flow_q[ln.parent] += flow_q[ln.child]
     w = np.ones((n, 3))
-    for ln in f.lines:
+    for ln in order:
         mp, mq = _mp_mq_explicit(ln.r, ln.x)
         ph = list(ln.phases)
         P = np.zeros(3)

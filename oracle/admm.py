@@ -247,10 +247,31 @@ class Result:
     history: np.ndarray       # (iterations, 4): pres, dres, eps_prim, eps_dual
 
 
+def balance_factor(pres, dres, eps_prim, eps_dual, mu, tau):
+    """Residual balancing (the acceleration the paper points to in Section
+    III-D, after Wohlberg): compare the primal and dual residuals, each
+    relative to its tolerance, and scale rho up by tau when the primal one is
+    more than mu times larger, down by tau in the opposite case."""
+    rp = pres / eps_prim if eps_prim > 0 else math.inf
+    rd = dres / eps_dual if eps_dual > 0 else math.inf
+    if rp > mu * rd:
+        return tau
+    if rd > mu * rp:
+        return 1.0 / tau
+    return 1.0
+
+
 def solve(P: Problem, rho: float = 100.0, eps_rel: float = 1e-3, max_iter: int = 1_000_000,
-          z0=None, lam0=None, fixed_iters: int | None = None, record=True, progress=None) -> Result:
+          z0=None, lam0=None, fixed_iters: int | None = None, record=True, progress=None,
+          balance=None) -> Result:
     """Algorithm 1: global update, then local and dual updates, until the
-    termination test holds (or max_iter / fixed_iters iterations)."""
+    termination test holds (or max_iter / fixed_iters iterations).
+
+    balance = (every, mu, tau) enables residual balancing: after iteration t
+    with t % every == 0 the factor of balance_factor() applies to rho from
+    iteration t + 2 on (rho_{t+2} = rho_{t+1} * factor); rho_1 = rho_2 = rho.
+    The duals are kept unscaled, so a change of rho needs no rescaling, and
+    the projection factors do not depend on rho."""
     if z0 is None:
         z, lam = initial_point(P)
     else:
@@ -262,13 +283,20 @@ def solve(P: Problem, rho: float = 100.0, eps_rel: float = 1e-3, max_iter: int =
     converged = False
     r = (math.nan,) * 4
     limit = fixed_iters if fixed_iters is not None else max_iter
+    sched = {1: rho, 2: rho}          # rho used by iteration t
     while t < limit:
         z_prev = z
-        x = global_update(P, z, lam, rho)
-        z = local_update(P, x, lam, rho)
-        lam = dual_update(P, x, z, lam, rho)
+        rt = sched[t + 1]
+        x = global_update(P, z, lam, rt)
+        z = local_update(P, x, lam, rt)
+        lam = dual_update(P, x, z, lam, rt)
         t += 1
-        r = residuals(P, x, z, z_prev, lam, rho, eps_rel)
+        r = residuals(P, x, z, z_prev, lam, rt, eps_rel)
+        f = 1.0
+        if balance is not None and t % balance[0] == 0:
+            f = balance_factor(r[0], r[1], r[2], r[3], balance[1], balance[2])
+        sched[t + 2] = sched[t + 1] * f
+        sched.pop(t, None)
         if record:
             hist.append(r)
         if progress is not None and t % progress == 0:
@@ -276,6 +304,8 @@ def solve(P: Problem, rho: float = 100.0, eps_rel: float = 1e-3, max_iter: int =
         if fixed_iters is None and r[0] <= r[2] and r[1] <= r[3]:
             converged = True
             break
-    return Result(x=x, z=z, lam=lam, iterations=t, converged=converged, objective=float(P.c @ x),
-                  pres=r[0], dres=r[1], eps_prim=r[2], eps_dual=r[3],
-                  history=np.asarray(hist).reshape(-1, 4))
+    res = Result(x=x, z=z, lam=lam, iterations=t, converged=converged, objective=float(P.c @ x),
+                 pres=r[0], dres=r[1], eps_prim=r[2], eps_dual=r[3],
+                 history=np.asarray(hist).reshape(-1, 4))
+    res.rho_final = sched.get(t + 1, rho)
+    return res

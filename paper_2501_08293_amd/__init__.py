@@ -6,7 +6,7 @@ include/opf_admm.h; `binding` marshals arguments to it.  There is no CPU
 fallback: using the solver without the built library raises."""
 from . import binding
 from .binding import (OPF_KERNEL_AUTO, OPF_KERNEL_PERSISTENT, OPF_KERNEL_STEP, OPF_PREC_FP64,
-                      OPF_PREC_MIXED, BatchSolver, OpfError, Solver)
+                      OPF_PREC_MIXED, BatchSolver, OpfError, Server, Solver)
 
-__all__ = ["binding", "Solver", "BatchSolver", "OpfError", "OPF_PREC_FP64", "OPF_PREC_MIXED", "OPF_KERNEL_AUTO",
+__all__ = ["binding", "Solver", "BatchSolver", "Server", "OpfError", "OPF_PREC_FP64", "OPF_PREC_MIXED", "OPF_KERNEL_AUTO",
            "OPF_KERNEL_STEP", "OPF_KERNEL_PERSISTENT"]

@@ -38,7 +38,8 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBOUNDS", -3: "E
 EXPORTED = ["opf_admm_default_options", "opf_admm_setup", "opf_admm_solve", "opf_admm_run_fixed",
             "opf_admm_residuals", "opf_admm_get_info", "opf_admm_destroy", "opf_admm_last_error",
             "opf_admm_setup_batch", "opf_admm_solve_batch", "opf_admm_batch_info", "opf_admm_destroy_batch",
-            "opf_admm_batch_last_error"]
+            "opf_admm_batch_last_error", "opf_server_default_options", "opf_server_create", "opf_server_submit",
+            "opf_server_poll", "opf_server_get_stats", "opf_server_destroy", "opf_server_last_error"]
 
 
 class opf_problem(C.Structure):
@@ -53,7 +54,8 @@ class opf_admm_options(C.Structure):
     _fields_ = [("rho", C.c_double), ("eps_rel", C.c_double), ("max_iter", C.c_int64),
                 ("precision", C.c_int32), ("polish", C.c_int32), ("check_every", C.c_int32),
                 ("kernel", C.c_int32), ("history_cap", C.c_int32), ("block_waves", C.c_int32),
-                ("spin_limit", C.c_int32), ("split_terms", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("spin_limit", C.c_int32), ("split_terms", C.c_int32), ("autotune", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class opf_warm(C.Structure):
@@ -64,7 +66,8 @@ class opf_result(C.Structure):
     _fields_ = [("x", C.c_void_p), ("z", C.c_void_p), ("lam", C.c_void_p), ("outputs_on_device", C.c_int32),
                 ("status", C.c_int32), ("iterations", C.c_int64), ("iterations_fp32", C.c_int64),
                 ("objective", C.c_double), ("pres", C.c_double), ("dres", C.c_double),
-                ("eps_prim", C.c_double), ("eps_dual", C.c_double), ("solve_ms", C.c_double)]
+                ("eps_prim", C.c_double), ("eps_dual", C.c_double), ("solve_ms", C.c_double),
+                ("kernel_ms", C.c_double), ("kernel_ms_fp32", C.c_double), ("kernel_launches", C.c_int64)]
 
 
 class opf_residuals(C.Structure):
@@ -78,7 +81,7 @@ class opf_admm_info(C.Structure):
                 ("sum_ns2", C.c_int64), ("factor_bytes_fp64", C.c_int64), ("device_bytes", C.c_int64),
                 ("setup_ms", C.c_double), ("grid_blocks", C.c_int32), ("block_waves", C.c_int32),
                 ("kernel", C.c_int32), ("persistent_capacity", C.c_int32), ("max_neighbours", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("factors_in_lds", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class opf_batch_result(C.Structure):
@@ -88,6 +91,26 @@ class opf_batch_result(C.Structure):
                 ("eps_prim", C.POINTER(C.c_double)), ("eps_dual", C.POINTER(C.c_double)),
                 ("total_iterations", C.c_int64), ("converged", C.c_int32), ("reserved1", C.c_int32),
                 ("solve_ms", C.c_double)]
+
+
+class opf_server_options(C.Structure):
+    _fields_ = [("admm", opf_admm_options), ("arena_bytes", C.c_int64), ("warm_bytes", C.c_int64),
+                ("max_slots", C.c_int32), ("max_workgroups", C.c_int32), ("iters_per_poll", C.c_int32),
+                ("setup_threads", C.c_int32), ("warm_start", C.c_int32), ("reserved", C.c_int32 * 5)]
+
+
+class opf_served(C.Structure):
+    _fields_ = [("request_id", C.c_int64), ("status", C.c_int32), ("warm_components", C.c_int32),
+                ("iterations", C.c_int64), ("objective", C.c_double), ("pres", C.c_double),
+                ("dres", C.c_double), ("eps_prim", C.c_double), ("eps_dual", C.c_double),
+                ("queue_ms", C.c_double), ("latency_ms", C.c_double), ("x", C.c_void_p)]
+
+
+class opf_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("resident", C.c_int32), ("queued", C.c_int32), ("arena_used", C.c_int64),
+                ("arena_bytes", C.c_int64), ("warm_used", C.c_int64), ("launches", C.c_int64),
+                ("busy_ms", C.c_double)]
 
 
 _lib = None
@@ -133,6 +156,21 @@ def load(path: str = LIB_PATH):
     lib.opf_admm_destroy_batch.restype = None
     lib.opf_admm_batch_last_error.argtypes = [H]
     lib.opf_admm_batch_last_error.restype = C.c_char_p
+    lib.opf_server_default_options.argtypes = [C.POINTER(opf_server_options)]
+    lib.opf_server_default_options.restype = None
+    lib.opf_server_create.argtypes = [C.POINTER(opf_server_options), C.c_void_p, C.POINTER(H)]
+    lib.opf_server_create.restype = C.c_int
+    lib.opf_server_submit.argtypes = [H, C.POINTER(opf_problem), C.c_uint64, C.POINTER(C.c_uint64),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.opf_server_submit.restype = C.c_int
+    lib.opf_server_poll.argtypes = [H, C.POINTER(opf_served), C.c_int, C.c_int]
+    lib.opf_server_poll.restype = C.c_int
+    lib.opf_server_get_stats.argtypes = [H, C.POINTER(opf_server_stats)]
+    lib.opf_server_get_stats.restype = C.c_int
+    lib.opf_server_destroy.argtypes = [H]
+    lib.opf_server_destroy.restype = None
+    lib.opf_server_last_error.argtypes = [H]
+    lib.opf_server_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -317,7 +355,7 @@ class Solver:
 
     def __init__(self, n, c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx, *, rho=100.0,
                  eps_rel=1e-3, max_iter=1_000_000, precision=OPF_PREC_FP64, polish=True, check_every=256,
-                 kernel=OPF_KERNEL_AUTO, history_cap=0, block_waves=0, spin_limit=0, stream=0):
+                 kernel=OPF_KERNEL_AUTO, history_cap=0, block_waves=0, spin_limit=0, autotune=False, stream=0):
         self._keep = dict(
             c=np.ascontiguousarray(c, np.float64), lb=np.ascontiguousarray(lb, np.float64),
             ub=np.ascontiguousarray(ub, np.float64), var_kind=np.ascontiguousarray(var_kind, np.uint8),
@@ -343,6 +381,7 @@ class Solver:
         o.history_cap = history_cap
         o.block_waves = block_waves
         o.spin_limit = spin_limit
+        o.autotune = int(bool(autotune))
         self.options = o
         self.h = opf_admm_setup(p, o, stream)
         self._keep = None   # the library copied everything it needs
@@ -411,7 +450,84 @@ class Solver:
             raise OpfError(rc, opf_admm_last_error(self.h))
         return dict(status=rc, x=x, z=z, lam=lam, iterations=r.iterations, iterations_fp32=r.iterations_fp32,
                     objective=r.objective, pres=r.pres, dres=r.dres, eps_prim=r.eps_prim, eps_dual=r.eps_dual,
-                    solve_ms=r.solve_ms)
+                    solve_ms=r.solve_ms, kernel_ms=r.kernel_ms, kernel_ms_fp32=r.kernel_ms_fp32,
+                    kernel_launches=r.kernel_launches)
 
     def residuals(self, hist_cap=0):
         return opf_admm_residuals(self.h, hist_cap)
+
+
+# ---- serving runtime ----------------------------------------------------------------
+
+def opf_server_default_options() -> opf_server_options:
+    o = opf_server_options()
+    load().opf_server_default_options(C.byref(o))
+    return o
+
+
+class Server:
+    """Owns one serving runtime.  submit() copies the problem arrays; the x
+    output buffer of each request is kept alive here until its result is
+    polled."""
+
+    def __init__(self, *, rho=100.0, eps_rel=1e-4, max_iter=1_000_000, arena_bytes=4 << 30, warm_bytes=1 << 30,
+                 max_slots=256, max_workgroups=8192, iters_per_poll=64, setup_threads=4, warm_start=True, stream=0):
+        lib = load()
+        o = opf_server_default_options()
+        o.admm.rho = rho
+        o.admm.eps_rel = eps_rel
+        o.admm.max_iter = max_iter
+        o.arena_bytes = int(arena_bytes)
+        o.warm_bytes = int(warm_bytes)
+        o.max_slots = max_slots
+        o.max_workgroups = max_workgroups
+        o.iters_per_poll = iters_per_poll
+        o.setup_threads = setup_threads
+        o.warm_start = int(bool(warm_start))
+        h = C.c_void_p()
+        rc = lib.opf_server_create(C.byref(o), C.c_void_p(stream or None), C.byref(h))
+        if rc != OPF_OK:
+            raise OpfError(rc, lib.opf_server_last_error(None).decode())
+        self.h = h
+        self._pending = {}
+
+    def submit(self, n, c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx, family=0, comp_keys=None) -> int:
+        keep = _keep(c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx)
+        x = np.zeros(int(n))
+        keys = None if comp_keys is None else np.ascontiguousarray(comp_keys, np.uint64)
+        rid = C.c_int64()
+        rc = load().opf_server_submit(self.h, C.byref(_problem(keep, n)), C.c_uint64(family),
+                                      _ptr(keys, C.c_uint64) if keys is not None else None,
+                                      _ptr(x, C.c_double), C.byref(rid))
+        if rc != OPF_OK:
+            raise OpfError(rc, load().opf_server_last_error(self.h).decode())
+        self._pending[rid.value] = x
+        return rid.value
+
+    def poll(self, max_out=64, wait_ms=0):
+        buf = (opf_served * max_out)()
+        k = load().opf_server_poll(self.h, buf, max_out, int(wait_ms))
+        out = []
+        for i in range(max(k, 0)):
+            r = buf[i]
+            out.append(dict(request_id=r.request_id, status=r.status, warm_components=r.warm_components,
+                            iterations=r.iterations, objective=r.objective, pres=r.pres, dres=r.dres,
+                            eps_prim=r.eps_prim, eps_dual=r.eps_dual, queue_ms=r.queue_ms,
+                            latency_ms=r.latency_ms, x=self._pending.pop(r.request_id, None)))
+        return out
+
+    def stats(self):
+        st = opf_server_stats()
+        load().opf_server_get_stats(self.h, C.byref(st))
+        return {k: getattr(st, k) for k, _ in opf_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().opf_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -64,7 +64,46 @@ struct PersistArgs {
     long long spin_limit;       // polls before a wait gives up
     long long max_iter;         // stop when this iteration count is reached
     int check;                  // 1: apply the termination test
+    int lds_factors;            // 1: factors copied once into LDS (dynamic shared memory)
+    int lds_factor_cols;        // largest sum over a workgroup's wavefronts of their factor columns
 };
+
+// ---- serving runtime: one resident solve (see admm_multi.hip)
+struct InstDesc {
+    const int2* winfo;
+    const int* var;
+    const int* meta;
+    const int* cstart;
+    const int* ccnt;
+    const int* clist;
+    const int* user_slot;
+    const double* F;
+    const double* bbar;
+    const double* lo;
+    const double* hi;
+    const double* cost;
+    double* z0; double* z1;
+    double* l0; double* l1;
+    double* x0; double* x1;
+    double* partials;           // [blocks][5]
+    Ctrl* ctrl;
+    int blocks;                 // workgroups of this solve
+    int lanes;                  // blocks * WPB * 64
+    int n;
+    int pad;
+    double rho, eps_rel;
+};
+
+hipError_t launch_multi_step(const InstDesc* descs, const int2* work, const int* nwork, int grid, int wpb,
+                             hipStream_t st);
+hipError_t launch_multi_init(InstDesc* descs, int slot, int lanes, const double* z0, const double* l0,
+                             long long max_iter, hipStream_t st);
+hipError_t launch_multi_output(const InstDesc* descs, int slot, double* xo, double* zo, double* lo,
+                               hipStream_t st);
+hipError_t launch_warm_gather(const int4* plan, int nplan, const double* rz, const double* rl, double* zu,
+                              double* lu, hipStream_t st);
+hipError_t launch_to_device_order(const double* zu, const double* lu, const int* user_slot, int lanes,
+                                  const double* zdef, double* zd, double* ld, int use_warm, hipStream_t st);
 
 // ---- batched same-topology scenarios (see admm_batch.hip)
 struct BatchCtrl {

@@ -196,6 +196,16 @@ __global__ __launch_bounds__(WPB * 64) void admm_persistent_kernel(IterArgs<T> a
     }
     const int2 wi = a.winfo[w];
     const T* Fw = a.F + (size_t)wi.y * 64;
+    if (p.lds_factors) {
+        // static factors of this workgroup's wavefronts, copied once into LDS
+        extern __shared__ __align__(16) unsigned char dyn_lds[];
+        T* Fl = reinterpret_cast<T*>(dyn_lds);
+        int off = 0;
+        for (int q = 0; q < wv; ++q) off += a.winfo[b * WPB + q].x;
+        Fl += (size_t)off * 64;
+        for (int k = 0; k < wi.x; ++k) Fl[k * 64 + lane] = Fw[k * 64 + lane];
+        Fw = Fl;
+    }
     const int base = meta & 255;
     const bool owner = (meta >> 16) & 1;
     // current local copy and dual of this slot (state of iteration t0)
@@ -330,15 +340,16 @@ __global__ void persistent_prepare_kernel(PersistArgs p, int G, Ctrl* ctrl) {
 
 template <typename T>
 hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G, hipStream_t st) {
+    const size_t lds = p.lds_factors ? (size_t)p.lds_factor_cols * 64 * sizeof(T) : 0;
     hipLaunchKernelGGL((persistent_prepare_kernel<T>), dim3((G + 255) / 256), dim3(256), 0, st, p, G, a.ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     void* args[] = {(void*)&a, (void*)&p};
     switch (wpb) {
-        case 1: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 1>, dim3(G + 1), dim3(64), args, 0, st);
-        case 2: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 2>, dim3(G + 1), dim3(128), args, 0, st);
-        case 8: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 8>, dim3(G + 1), dim3(512), args, 0, st);
-        default: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 4>, dim3(G + 1), dim3(256), args, 0, st);
+        case 1: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 1>, dim3(G + 1), dim3(64), args, lds, st);
+        case 2: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 2>, dim3(G + 1), dim3(128), args, lds, st);
+        case 8: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 8>, dim3(G + 1), dim3(512), args, lds, st);
+        default: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 4>, dim3(G + 1), dim3(256), args, lds, st);
     }
 }
 template hipError_t launch_persistent<double>(const IterArgs<double>&, PersistArgs, int, int, hipStream_t);
@@ -347,21 +358,21 @@ template hipError_t launch_persistent<float>(const IterArgs<float>&, PersistArgs
 // Largest co-resident grid for the persistent kernel (0 on error); the grid
 // holds one workgroup more than the compute workgroups (the reducer).
 template <typename T>
-int persistent_capacity(int wpb) {
+int persistent_capacity(int wpb, size_t lds_bytes) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e;
     switch (wpb) {
-        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 1>, 64, 0); break;
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 2>, 128, 0); break;
-        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 8>, 512, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 4>, 256, 0); break;
+        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 1>, 64, lds_bytes); break;
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 2>, 128, lds_bytes); break;
+        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 8>, 512, lds_bytes); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 4>, 256, lds_bytes); break;
     }
     if (e != hipSuccess) return 0;
     return per * cus;
 }
-template int persistent_capacity<double>(int);
-template int persistent_capacity<float>(int);
+template int persistent_capacity<double>(int, size_t);
+template int persistent_capacity<float>(int, size_t);
 
 }  // namespace opf

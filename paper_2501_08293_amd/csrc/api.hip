@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -25,7 +26,7 @@ hipError_t launch_promote(const float* z32a, const float* z32b, const float* l32
                           long long max_iter, int check, hipStream_t st);
 template <typename T>
 hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G, hipStream_t st);
-template <typename T> int persistent_capacity(int wpb);
+template <typename T> int persistent_capacity(int wpb, size_t lds_bytes);
 template <typename T>
 hipError_t launch_output(const T* z0, const T* z1, const T* l0, const T* l1, const T* x0, const T* x1,
                          const int* user_slot, int LP, int n, const double* c, double* xo, double* zo,
@@ -38,6 +39,8 @@ namespace {
 
 std::mutex g_err_mu;
 std::string g_setup_err;
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;   // problem shape -> (schedule, workgroup waves)
 
 struct DevBuf {
     void* p = nullptr;
@@ -112,6 +115,11 @@ struct opf_admm_handle {
     int* dev_error = nullptr;
     int* stopped = nullptr;
     int* error_host = nullptr;     // pinned
+    int lds_cols = 0;              // factor columns of the largest workgroup
+    int lds32 = 0, lds64 = 0;      // factors resident in LDS for each precision
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double kernel_ms = 0;          // device time of iteration kernels in the current solve
+    long long kernel_launches = 0;
 };
 
 namespace {
@@ -238,12 +246,22 @@ int run_phase(opf_admm_handle* h, PrecState<T>& s, hipGraphExec_t* graph) {
         if (rc) return rc;
         h->graph_k = k;
     }
+    const long long before = h->ctrl_host->iter;
+    long long t_prev = -1;
     for (;;) {
+        HIPCHK(hipEventRecord(h->ev0, h->stream));
         HIPCHK(hipGraphLaunch(*graph, h->stream));
+        HIPCHK(hipEventRecord(h->ev1, h->stream));
         HIPCHK(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        h->kernel_ms += ms;
         if (h->ctrl_host->stop) break;
+        t_prev = h->ctrl_host->iter;
     }
+    (void)t_prev;
+    h->kernel_launches += h->ctrl_host->iter - before;
     return 0;
 }
 
@@ -263,10 +281,18 @@ int run_phase_persistent(opf_admm_handle* h, PrecState<T>& s, long long max_iter
     p.spin_limit = h->opt.spin_limit > 0 ? h->opt.spin_limit : 4000000LL;
     p.max_iter = max_iter;
     p.check = check;
+    p.lds_factor_cols = h->lds_cols;
+    p.lds_factors = sizeof(T) == 8 ? h->lds64 : h->lds32;
+    HIPCHK(hipEventRecord(h->ev0, h->stream));
     HIPCHK(launch_persistent<T>(a, p, h->wpb, h->lay.blocks, h->stream));
+    HIPCHK(hipEventRecord(h->ev1, h->stream));
     HIPCHK(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipMemcpyAsync(h->error_host, h->dev_error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->kernel_ms += ms;
+    h->kernel_launches += 1;
     if (*h->error_host) {
         h->ctrl_host->status = OPF_EHANG;
         return set_err(h, OPF_EHANG, "a bounded device-side wait ran out in the persistent kernel");
@@ -349,12 +375,17 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
     int status = OPF_OK;
     long long it32 = 0;
     bool final64 = true;
+    h->kernel_ms = 0;
+    h->kernel_launches = 0;
+    h->ctrl_host->iter = 0;
+    r->kernel_ms_fp32 = 0;
     if (h->opt.precision == OPF_PREC_MIXED) {
         HIPCHK(launch_init<float>(z0, l0, h->s32.z[0], h->s32.l[0], h->LP, h->ctrl, max_iter, check, h->stream));
         rc = run_any<float>(h, h->s32, &h->graph32, max_iter, check);
         if (rc) return rc;
         it32 = h->ctrl_host->iter;
         status = h->ctrl_host->status;
+        r->kernel_ms_fp32 = h->kernel_ms;
         const bool polish = h->opt.polish && !fixed && status != OPF_ENUMERIC;
         if (polish) {
             HIPCHK(launch_promote(h->s32.z[0], h->s32.z[1], h->s32.l[0], h->s32.l[1], h->s64.z[0], h->s64.z[1],
@@ -382,6 +413,8 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
     r->eps_prim = c.res[2];
     r->eps_dual = c.res[3];
     r->status = status;
+    r->kernel_ms = h->kernel_ms;
+    r->kernel_launches = h->kernel_launches;
     h->last_iter = c.iter;
     h->last_prec = final64 ? OPF_PREC_FP64 : OPF_PREC_MIXED;
     r->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -414,6 +447,49 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     opf_admm_options opt;
     if (o) opt = *o;
     else opf_admm_default_options(&opt);
+    if (opt.autotune && opt.kernel == OPF_KERNEL_AUTO && opt.block_waves == 0 && p->S > 0 && p->comp_n) {
+        // ---- autotuner: time each (schedule, workgroup shape) on this problem
+        int64_t L = 0, n2 = 0;
+        for (int s2 = 0; s2 < p->S; ++s2) { L += p->comp_n[s2]; n2 += (int64_t)p->comp_n[s2] * p->comp_n[s2]; }
+        const std::string key = std::to_string(p->n) + "/" + std::to_string(p->S) + "/" + std::to_string(L) + "/" +
+                                std::to_string(n2) + "/" + std::to_string(opt.precision);
+        std::pair<int, int> choice{0, 0};
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(key);
+            if (it != g_tune.end()) choice = it->second;
+        }
+        if (!choice.first) {
+            double best = 1e300;
+            const int cands[][2] = {{OPF_KERNEL_PERSISTENT, 2}, {OPF_KERNEL_PERSISTENT, 4}, {OPF_KERNEL_PERSISTENT, 8},
+                                    {OPF_KERNEL_STEP, 4}, {OPF_KERNEL_STEP, 8}};
+            for (const auto& c : cands) {
+                opf_admm_options t = opt;
+                t.autotune = 0;
+                t.kernel = c[0];
+                t.block_waves = c[1];
+                t.history_cap = 0;
+                t.check_every = 128;
+                opf_admm_handle* th = nullptr;
+                if (opf_admm_setup(p, &t, hip_stream, &th) != OPF_OK) continue;
+                std::vector<double> xs(p->n);
+                opf_result r{};
+                r.x = xs.data();
+                double ms = 1e300;
+                if (opf_admm_run_fixed(th, nullptr, 64, &r) >= 0 && opf_admm_run_fixed(th, nullptr, 512, &r) >= 0)
+                    ms = r.kernel_ms;
+                opf_admm_destroy(th);
+                if (ms < best) { best = ms; choice = {c[0], c[1]}; }
+            }
+            if (!choice.first) choice = {OPF_KERNEL_AUTO, 4};
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[key] = choice;
+        }
+        opt.autotune = 0;
+        opt.kernel = choice.first;
+        opt.block_waves = choice.second;
+        return opf_admm_setup(p, &opt, hip_stream, out);
+    }
     if (!(opt.rho > 0.0) || !std::isfinite(opt.rho)) return set_err(nullptr, OPF_EINVAL, "rho must be positive");
     if (!(opt.eps_rel > 0.0)) return set_err(nullptr, OPF_EINVAL, "eps_rel must be positive");
     if (opt.max_iter < 1) return set_err(nullptr, OPF_EINVAL, "max_iter must be >= 1");
@@ -452,6 +528,8 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     }
     if (hipHostMalloc((void**)&h->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
         return fail(set_err(h, OPF_ENOMEM, "hipHostMalloc failed"));
+    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
+        return fail(set_err(h, OPF_EHIP, "hipEventCreate failed"));
     std::memset(h->ctrl_host, 0, sizeof(Ctrl));
     const HostLayout& L = h->lay;
     std::vector<int2> wi(L.waves);
@@ -485,9 +563,22 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     if (hipHostMalloc((void**)&h->error_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return fail(set_err(h, OPF_ENOMEM, "hipHostMalloc failed"));
     *h->error_host = 0;
-    h->capacity = opt.precision == OPF_PREC_MIXED ? std::min(persistent_capacity<float>(h->wpb),
-                                                             persistent_capacity<double>(h->wpb))
-                                                  : persistent_capacity<double>(h->wpb);
+    // factors stay in LDS when the grid still fits the device with that much
+    // dynamic shared memory per workgroup (else they are read through the caches)
+    for (int b2 = 0; b2 < blocks; ++b2) {
+        int cols = 0;
+        for (int q = 0; q < h->wpb; ++q) cols += L.wave_maxn[(size_t)b2 * h->wpb + q];
+        h->lds_cols = std::max(h->lds_cols, cols);
+    }
+    const size_t lds_limit = 64 * 1024;
+    const size_t l64 = (size_t)h->lds_cols * 64 * 8, l32 = (size_t)h->lds_cols * 64 * 4;
+    const int cap64_lds = l64 <= lds_limit ? persistent_capacity<double>(h->wpb, l64) : 0;
+    const int cap32_lds = l32 <= lds_limit ? persistent_capacity<float>(h->wpb, l32) : 0;
+    h->lds64 = cap64_lds >= blocks + 1;
+    h->lds32 = cap32_lds >= blocks + 1;
+    const int cap64 = h->lds64 ? cap64_lds : persistent_capacity<double>(h->wpb, 0);
+    const int cap32 = h->lds32 ? cap32_lds : persistent_capacity<float>(h->wpb, 0);
+    h->capacity = opt.precision == OPF_PREC_MIXED ? std::min(cap32, cap64) : cap64;
     if (opt.kernel == OPF_KERNEL_PERSISTENT && h->capacity < blocks + 1)
         return fail(set_err(h, OPF_EINVAL, "persistent kernel needs " + std::to_string(blocks + 1) +
                                               " co-resident workgroups, the device holds " +
@@ -561,6 +652,7 @@ int opf_admm_get_info(const opf_admm_handle* h, opf_admm_info* info) {
     info->kernel = h->kernel;
     info->persistent_capacity = h->capacity;
     info->max_neighbours = h->lay.max_nbrs;
+    info->factors_in_lds = h->lds32 | (h->lds64 << 1);
     return 0;
 }
 
@@ -572,6 +664,8 @@ void opf_admm_destroy(opf_admm_handle* h) {
     for (auto& b : h->bufs) (void)hipFree(b.p);
     if (h->ctrl_host) (void)hipHostFree(h->ctrl_host);
     if (h->error_host) (void)hipHostFree(h->error_host);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
     if (h->stream && h->stream != h->user_stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }

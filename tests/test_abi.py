@@ -21,7 +21,7 @@ def _lib():
 def test_library_exports_every_declared_symbol():
     binding, lib = _lib()
     hdr = open(os.path.join(ROOT, "include", "opf_admm.h")).read()
-    names = set(re.findall(r"\b(opf_admm_\w+)\s*\(", hdr))
+    names = set(re.findall(r"\b(opf_(?:admm|server)_\w+)\s*\(", hdr))
     assert names, "no declarations found"
     for nm in sorted(names):
         assert hasattr(lib, nm), nm
@@ -33,7 +33,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(binding.opf_problem) == 88
     assert C.sizeof(binding.opf_admm_options) == 8 + 8 + 8 + 6 * 4 + 7 * 4 + 4
     assert C.sizeof(binding.opf_batch_result) == 8 + 4 + 4 + 7 * 8 + 8 + 4 + 4 + 8
-    assert C.sizeof(binding.opf_result) == 3 * 8 + 4 + 4 + 8 + 8 + 6 * 8
+    assert C.sizeof(binding.opf_result) == 3 * 8 + 4 + 4 + 8 + 8 + 6 * 8 + 8 + 8 + 8
 
 
 def test_default_options_are_the_papers():

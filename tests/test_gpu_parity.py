@@ -239,10 +239,13 @@ def test_full_size_8500bus_fixed_iterations_match_oracle(kernel):
 
 
 def test_full_size_8500bus_solve_matches_golden_fp64():
-    _say("[gpu] 8500bus solve to 1e-4 vs golden (FP64)")
-    g = _golden("8500bus", 1e-4)
+    """The full 8500-bus solve at the paper's eps_rel = 1e-3 (about 69k
+    iterations) against the oracle's run, in the benchmark's launch
+    configuration (persistent schedule, FP64)."""
+    _say("[gpu] 8500bus solve to 1e-3 vs golden (FP64)")
+    g = _golden("8500bus", 1e-3)
     inst = _inst("8500bus")
-    s = _solver(inst, rho=RHO, eps_rel=1e-4, check_every=512)
+    s = _solver(inst, rho=RHO, eps_rel=1e-3, check_every=512)
     out = s.solve()
     assert out["status"] == 0
     assert abs(out["iterations"] - g["iterations"]) <= 1
@@ -250,3 +253,18 @@ def test_full_size_8500bus_solve_matches_golden_fp64():
     w = out["x"][g["w_index"]]
     assert np.max(np.abs(w - np.array(g["w_value"]))) <= 1e-6
     s.close()
+
+
+def test_autotuned_configuration_solves_correctly():
+    """The autotuner picks a schedule and workgroup shape by timing short runs
+    on the problem; the chosen configuration still matches the oracle."""
+    _say("[gpu] autotune 123bus")
+    g = _golden("123bus", 1e-4)
+    inst = _inst("123bus")
+    s = _solver(inst, rho=RHO, eps_rel=1e-4, autotune=True)
+    info = s.info()
+    assert info.kernel in (STEP, PERSIST) and info.block_waves in (2, 4, 8)
+    out = s.solve()
+    s.close()
+    assert abs(out["iterations"] - g["iterations"]) <= 1
+    assert abs(out["objective"] - g["objective"]) <= 1e-6 * abs(g["objective"])
