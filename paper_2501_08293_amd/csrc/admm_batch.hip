@@ -30,6 +30,8 @@
 namespace opf {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBatchCopies = 6;    // copies per variable gathered from registers (more: from memory)
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
@@ -73,29 +75,72 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     const int w = blockIdx.x;
     const int kc = blockIdx.y * 64;
 
-    // ---- phase 1: consensus average and projection input, 16 slots per wave
+    // ---- slot descriptors of this wavefront staged in LDS (one load per thread)
+    __shared__ int s_var[64], s_cn[64], s_cs[64], s_owner[64];
+    __shared__ float s_cost[64], s_lo[64], s_hi[64];
+    __shared__ int s_copy[64][kBatchCopies];
+    if (tid < 64) {
+        const int d = w * 64 + tid;
+        const int g = a.var[d];
+        s_var[tid] = g;
+        int cn = 0, cs = 0;
+        if (g >= 0) {
+            cn = a.ccnt[d];
+            cs = a.cstart[d];
+            s_owner[tid] = (a.meta[d] >> 16) & 1;
+            s_cost[tid] = a.cost[d] * a.inv_rho;
+            s_lo[tid] = a.lo[d];
+            s_hi[tid] = a.hi[d];
+        }
+        s_cn[tid] = cn;
+        s_cs[tid] = cs;
+#pragma unroll
+        for (int q = 0; q < kBatchCopies; ++q) s_copy[tid][q] = q < cn ? a.clist[cs + q] : d;
+    }
+    __syncthreads();
+
+    // ---- phase 1: consensus average and projection input, 16 slots per
+    // wave in groups of four whose gathers are in flight together
     {
-        const int k = kc + lane;
-#pragma unroll 4
-        for (int rr = 0; rr < 16; ++rr) {
-            const int r = wv * 16 + rr;
-            const int d = w * 64 + r;
-            const int g = a.var[d];
-            float xv = 0.0f, vv = 0.0f;
-            if (g >= 0) {
-                const int cs = a.cstart[d], cn = a.ccnt[d];
-                float acc = 0.0f;
-                for (int q = 0; q < cn; ++q) {
-                    const size_t e = (size_t)a.clist[cs + q];
-                    acc += zp[e * Kp + k] - lp[e * Kp + k] * a.inv_rho;
+        const size_t k = (size_t)(kc + lane);
+#pragma unroll
+        for (int r0 = 0; r0 < 16; r0 += 4) {
+            float zz[4][kBatchCopies], ll[4][kBatchCopies], lown[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = wv * 16 + r0 + j;
+                const int cn = s_cn[r];
+#pragma unroll
+                for (int q = 0; q < kBatchCopies; ++q) {
+                    const size_t e = (size_t)s_copy[r][q];
+                    zz[j][q] = q < cn ? zp[e * Kp + k] : 0.0f;
+                    ll[j][q] = q < cn ? lp[e * Kp + k] : 0.0f;
                 }
-                const float xh = (acc - a.cost[d] * a.inv_rho) / (float)cn;
-                xv = xh < a.lo[d] ? a.lo[d] : (xh > a.hi[d] ? a.hi[d] : xh);
-                vv = xv + lp[(size_t)d * Kp + k] * a.inv_rho;
-                if ((a.meta[d] >> 16) & 1) xq[(size_t)g * Kp + k] = xv;
+                lown[j] = s_var[r] >= 0 ? lp[(size_t)(w * 64 + r) * Kp + k] : 0.0f;
             }
-            xs[r][lane] = xv;
-            vs[r][lane] = vv;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = wv * 16 + r0 + j;
+                const int g = s_var[r];
+                const int cn = s_cn[r];
+                float xv = 0.0f, vv = 0.0f;
+                if (g >= 0) {
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < kBatchCopies; ++q)
+                        if (q < cn) acc += zz[j][q] - ll[j][q] * a.inv_rho;
+                    for (int q = kBatchCopies; q < cn; ++q) {
+                        const size_t e = (size_t)a.clist[s_cs[r] + q];
+                        acc += zp[e * Kp + k] - lp[e * Kp + k] * a.inv_rho;
+                    }
+                    const float xh = (acc - s_cost[r]) / (float)cn;
+                    xv = xh < s_lo[r] ? s_lo[r] : (xh > s_hi[r] ? s_hi[r] : xh);
+                    vv = xv + lown[j] * a.inv_rho;
+                    if (s_owner[r]) xq[(size_t)g * Kp + k] = xv;
+                }
+                xs[r][lane] = xv;
+                vs[r][lane] = vv;
+            }
         }
     }
     __syncthreads();
