@@ -170,7 +170,7 @@ struct opf_server {
     Ctrl* h_ctrls = nullptr;
     int2* h_work = nullptr;
     int* h_nwork = nullptr;
-    hipGraphExec_t graph = nullptr;
+    std::map<int, hipGraphExec_t> graphs;  // grid size -> graph of iters_per_poll shared launches
     std::vector<Slot> slots;
     int active = 0, active_blocks = 0;
     bool dirty = true;
@@ -481,6 +481,25 @@ bool retire(opf_server* s, int slot_id) {
     return true;
 }
 
+// Graph of `iters_per_poll` shared launches over a grid of `grid` workgroups
+// (grids come in powers of two so that few graphs cover every mix).
+hipGraphExec_t graph_for(opf_server* s, int grid) {
+    auto it = s->graphs.find(grid);
+    if (it != s->graphs.end()) return it->second;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    bool ok = true;
+    for (int i = 0; i < s->opt.iters_per_poll && ok; ++i)
+        ok = launch_multi_step(s->d_descs, s->d_work, s->d_nwork, grid, kWPB, s->stream) == hipSuccess;
+    if (hipStreamEndCapture(s->stream, &g) != hipSuccess) ok = false;
+    if (ok && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) ok = false;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) return nullptr;
+    s->graphs[grid] = ge;
+    return ge;
+}
+
 void worker_loop(opf_server* s) {
     const int k = std::max(1, s->opt.iters_per_poll);
     for (;;) {
@@ -506,8 +525,16 @@ void worker_loop(opf_server* s) {
             }
             s->dirty = false;
         }
+        int grid = 64;
+        while (grid < *s->h_nwork) grid *= 2;
+        grid = std::min(grid, s->opt.max_workgroups);
+        hipGraphExec_t graph = graph_for(s, grid);
+        if (!graph) {
+            serr(s, OPF_EHIP, "graph capture failed");
+            return;
+        }
         const auto t0 = clk::now();
-        if (hipGraphLaunch(s->graph, s->stream) != hipSuccess ||
+        if (hipGraphLaunch(graph, s->stream) != hipSuccess ||
             hipMemcpyAsync(s->h_ctrls, s->d_ctrls, sizeof(Ctrl) * s->slots.size(), hipMemcpyDeviceToHost,
                            s->stream) != hipSuccess ||
             hipStreamSynchronize(s->stream) != hipSuccess) {
@@ -580,20 +607,6 @@ int opf_server_create(const opf_server_options* o, void* hip_stream, opf_server*
         hipStreamSynchronize(s->stream) != hipSuccess)
         return fail(OPF_EHIP, "device initialisation failed");
     s->slots.resize(MS);
-    // one graph of `iters_per_poll` shared launches over the fixed grid
-    hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return fail(OPF_EHIP, "capture failed");
-    for (int i = 0; i < opt.iters_per_poll; ++i)
-        if (launch_multi_step(s->d_descs, s->d_work, s->d_nwork, MW, kWPB, s->stream) != hipSuccess) {
-            (void)hipStreamEndCapture(s->stream, &g);
-            if (g) (void)hipGraphDestroy(g);
-            return fail(OPF_EHIP, "launch during capture failed");
-        }
-    if (hipStreamEndCapture(s->stream, &g) != hipSuccess) return fail(OPF_EHIP, "capture failed");
-    const hipError_t e = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return fail(OPF_EHIP, "graph instantiation failed");
     opf_server* raw = s.release();
     for (int t = 0; t < raw->opt.setup_threads; ++t) raw->setup_threads.emplace_back(setup_loop, raw);
     raw->worker = std::thread(worker_loop, raw);
@@ -685,7 +698,7 @@ void opf_server_destroy(opf_server* s) {
         (void)hipFree(w.second.z);
         (void)hipFree(w.second.l);
     }
-    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.second);
     if (s->arena_base) (void)hipFree(s->arena_base);
     if (s->d_descs) (void)hipFree(s->d_descs);
     if (s->d_work) (void)hipFree(s->d_work);
