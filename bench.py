@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--kernel", default="auto", choices=["auto", "step", "persistent"])
     ap.add_argument("--block-waves", type=int, default=0)
+    ap.add_argument("--workgroup-order", type=int, default=0, choices=[0, 1],
+                    help="persistent kernel: 0 = XCD-contiguous packing ranges, 1 = hardware order")
     ap.add_argument("--check-every", type=int, default=1024)
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="time this many iterations per step instead of solving to tolerance")
@@ -71,6 +73,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-eps", type=float, default=1e-3)
+    ap.add_argument("--only", choices=["batch", "serve"], default=None,
+                    help="run only this leg and print its record (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (counter calibration for profiles)")
     return ap.parse_args()
@@ -137,7 +141,8 @@ def single_instance(args, torch):
     kern = {"auto": 0, "step": 1, "persistent": 2}[args.kernel]
     flat = (inst.n, inst.c, inst.lb, inst.ub, inst.var_kind) + tuple(inst.flat())
     solver = Solver(*flat, rho=100.0, eps_rel=args.eps, precision=prec, check_every=args.check_every,
-                    kernel=kern, block_waves=args.block_waves, stream=stream.cuda_stream)
+                    kernel=kern, block_waves=args.block_waves, workgroup_order=args.workgroup_order,
+                    stream=stream.cuda_stream)
     info = solver.info()
     x = torch.zeros(inst.n, dtype=torch.float64, device=dev)
     fixed = args.fixed_iters or None
@@ -354,6 +359,10 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.only:
+        leg = batch_leg(args, torch) if args.only == "batch" else serve_leg(args, torch)
+        print(json.dumps({args.only: leg}), flush=True)
         return
     line, inst = single_instance(args, torch)
     if not args.skip_batch:

@@ -115,7 +115,9 @@ typedef struct opf_admm_options {
     int32_t autotune;       /* 1: with kernel AUTO and block_waves 0, time short runs of each
                                schedule and workgroup shape on this problem and keep the fastest
                                (decisions cached per problem shape for the process) */
-    int32_t reserved[4];
+    int32_t workgroup_order; /* PERSISTENT: 0 = each XCD runs a contiguous range of the packed
+                               workgroups (neighbours share an L2), 1 = hardware order */
+    int32_t reserved[3];
 } opf_admm_options;
 
 /* Optional warm start: z0 and lambda0 in user slot order (length L). */
@@ -284,8 +286,11 @@ typedef struct opf_server_options {
     int64_t arena_bytes;       /* device memory for resident solves (admission budget) */
     int64_t warm_bytes;        /* device memory for warm-start states (least recently used evicted) */
     int32_t max_slots;         /* most solves resident at once */
-    int32_t max_workgroups;    /* grid of the shared launch (sum of resident workgroups) */
-    int32_t iters_per_poll;    /* iterations between host polls of the stop flags */
+    int32_t max_workgroups;    /* cap on the grid of the shared launch (sum over resident solves of their
+                                  workgroups + 1); the device's co-resident capacity caps it too, and a
+                                  solve that can never fit is answered with OPF_ENOMEM */
+    int32_t iters_per_poll;    /* iterations each resident solve runs per shared launch before the host
+                                  polls the stop flags and admits / retires solves */
     int32_t setup_threads;     /* host threads for row reduction / factors / packing */
     int32_t warm_start;        /* 1: use resident states of the same family */
     int32_t reserved[5];

@@ -8,6 +8,34 @@
 
 namespace opf {
 
+// ---- arithmetic of one iteration, shared by every schedule (single-instance
+// step and persistent kernels, serving kernel) with explicit fused
+// multiply-adds, so that all schedules round identically.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// term of one copy in the consensus sum of global_sparse: z_e - lambda_e / rho
+template <typename T>
+__device__ __forceinline__ T copy_term(T z, T l, T inv_rho) {
+    return fmadd(-l, inv_rho, z);
+}
+// global_sparse: clipped average of the copy terms, shifted by the cost term
+template <typename T>
+__device__ __forceinline__ T consensus_value(T acc, T cost, T inv_rho, int copies, T lo, T hi) {
+    const T xh = fmadd(-cost, inv_rho, acc) / (T)copies;
+    return xh < lo ? lo : (xh > hi ? hi : xh);
+}
+// input of the local projection closed_2: B_s x + lambda_s / rho
+template <typename T>
+__device__ __forceinline__ T projection_input(T x, T l, T inv_rho) {
+    return fmadd(l, inv_rho, x);
+}
+// dual update ADMM-3: lambda_s + rho (B_s x - x_s)
+template <typename T>
+__device__ __forceinline__ T dual_step(T l, T rho, T x, T z) {
+    return fmadd(rho, x - z, l);
+}
+
 // Control block in device memory; written by the last workgroup of each
 // iteration, read by the host between launches and by the next iteration.
 struct Ctrl {
@@ -52,23 +80,26 @@ struct IterArgs {
 
 // Extra state of the persistent kernel (see admm_persistent.hip).
 struct PersistArgs {
-    const int* nbr_ptr;         // [G + 1] neighbour lists of each workgroup
-    const int* nbr_list;
-    long long* flags;           // [G] last iteration published by each workgroup
-    unsigned* arrive;           // [2] arrivals per iteration parity
-    double* partials;           // [2][G][5] residual partial sums per parity
-    long long* dec_iter;        // [2] iteration whose stop decision the slot holds
-    int* dec_stop;              // [2]
+    unsigned long long* pub;    // [2][LP][words] published copy terms with iteration tags
+    long long* flags;           // [G] iteration whose residual partials each workgroup has completed
+    double* partials;           // [kDecisionLag][G][5] residual partial sums
+    long long* dec_iter;        // last iteration the reducer has decided
+    long long* dec_stop;        // stop iteration, -1 while running
     int* error;                 // OPF_EHANG when a bounded wait ran out
-    int* stopped;               // a stop has been decided in this launch
     long long spin_limit;       // polls before a wait gives up
     long long max_iter;         // stop when this iteration count is reached
     int check;                  // 1: apply the termination test
     int lds_factors;            // 1: factors copied once into LDS (dynamic shared memory)
     int lds_factor_cols;        // largest sum over a workgroup's wavefronts of their factor columns
+    int xcd_remap;              // 1: consecutive workgroups of the packing share an XCD
 };
 
-// ---- serving runtime: one resident solve (see admm_multi.hip)
+// Iterations between a residual reduction and the moment workgroups act on
+// its stop decision (also the depth of the partial-sum ring and of the state
+// history each slot keeps in registers).
+constexpr int kDecisionLag = 3;
+
+// ---- serving runtime: one resident solve (see admm_multi.hip, admm_persistent.hip)
 struct InstDesc {
     const int2* winfo;
     const int* var;
@@ -85,17 +116,31 @@ struct InstDesc {
     double* z0; double* z1;
     double* l0; double* l1;
     double* x0; double* x1;
-    double* partials;           // [blocks][5]
+    double* partials;           // [kDecisionLag][blocks][5]
+    unsigned long long* pub;    // [2][lanes][2] published copy terms (persistent schedule)
+    long long* flags;           // [blocks]
+    long long* dec;             // [2]: last decided iteration, stop iteration
     Ctrl* ctrl;
     int blocks;                 // workgroups of this solve
     int lanes;                  // blocks * WPB * 64
     int n;
-    int pad;
+    int lds_factors;            // 1: the factors of each workgroup fit the launch's LDS budget
     double rho, eps_rel;
 };
 
-hipError_t launch_multi_step(const InstDesc* descs, const int2* work, const int* nwork, int grid, int wpb,
-                             hipStream_t st);
+// Launch-wide arguments of the persistent serving kernel.
+struct ServeArgs {
+    int* error;                 // OPF_EHANG when a bounded wait ran out (shared by all solves)
+    long long spin_limit;
+    long long chunk;            // iterations per launch before a solve pauses
+    int xcd_remap;
+    int lds_cols;               // factor columns of the dynamic LDS budget per workgroup
+};
+
+hipError_t launch_serve_persistent(const InstDesc* descs, const int2* work, int nwork, const ServeArgs& s,
+                                   hipStream_t st);
+int serve_capacity(size_t lds_bytes);
+
 hipError_t launch_multi_init(InstDesc* descs, int slot, int lanes, const double* z0, const double* l0,
                              long long max_iter, hipStream_t st);
 hipError_t launch_multi_output(const InstDesc* descs, int slot, double* xo, double* zo, double* lo,

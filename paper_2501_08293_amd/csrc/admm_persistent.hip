@@ -2,27 +2,35 @@
 // launch runs every iteration of Algorithm 1 until the termination test holds.
 //
 // Work split: workgroup b owns `WPB` packed wavefronts (a contiguous run of the
-// component graph) and keeps its slots' static data and its own local copy
-// and dual in registers across iterations.  Synchronisation is local:
-//   * before iteration t+1, workgroup b waits until every workgroup owning a
-//     copy of one of its variables ("neighbour") has published iteration t
-//     (a per-workgroup iteration flag);
-//   * the stacked z and lambda live in two buffers (iteration parity); a
-//     neighbour has finished reading buffer (t-1)&1 once it publishes t, so
-//     writing buffer (t+1)&1 is safe after the same wait;
-//   * every workgroup publishes its residual partial sums of iteration t with
-//     its flag; one extra workgroup (the reducer, the last of the grid) waits
-//     for all flags to reach t, reduces the partials in a fixed order and
-//     publishes the stop decision for t.  Workgroups consult it one iteration
-//     later (before starting t+2), so the reduction is hidden behind
-//     iteration t+1, whose writes go to the other buffer and leave the state
-//     of t intact.  No read-modify-write atomics are on the compute path.
+// component graph) and keeps its slots' static data, its factors (in LDS when
+// they fit) and its own local copy and dual in registers across iterations.
+//
+// Data exchange without barriers or flags on the compute path: after
+// iteration t every slot publishes the one value other copies of its variable
+// need, its consensus term z - lambda / rho, as 64-bit words that carry the
+// iteration number t in their upper half (one word for FP32, two for FP64).
+// A consumer loads the words of all copies of its variable at once and only
+// re-loads those whose tag is not yet t.  Two buffers (iteration parity)
+// suffice: a slot can publish t + 1 only after it has read every neighbour's
+// term of t, which each neighbour computed after reading the old term of
+// t - 1 that t + 1 overwrites.
+//
+// Termination: each workgroup writes its FP64 residual partial sums of
+// iteration t into a ring of kDecisionLag slots and, one iteration later
+// (after the wait for its gathers has also completed those stores), an
+// iteration flag.  One extra workgroup (the reducer, last of the grid) waits
+// for every flag, reduces the partials in a fixed order and publishes the last
+// decided iteration and, on a stop, the stop iteration ts.  A workgroup acts
+// on the decision of iteration tn - kDecisionLag at the start of tn, so every
+// workgroup computes exactly the iterations up to ts + kDecisionLag - 1 (no
+// wait can outlive its producer), and keeps the state of its last
+// kDecisionLag iterations in registers to write out the state of ts.
 // Cross-workgroup data moves through agent-scope atomic loads and stores
-// (coherent across the chip's L2 slices without write-back fences); ordering
-// between a workgroup's data stores and its flag store is an explicit wait for
-// outstanding memory operations followed by a workgroup barrier.
-// Every wait is bounded: a wait that runs out sets OPF_EHANG and every
-// workgroup leaves the loop, so the grid always drains.
+// (coherent across the chip's L2 slices without write-back fences).  Every
+// wait is bounded: a wait that runs out sets OPF_EHANG and every workgroup
+// leaves the loop, so the grid always drains.
+#include <algorithm>
+
 #include "admm_kernels.h"
 
 #include "../../include/opf_admm.h"
@@ -49,140 +57,254 @@ __device__ __forceinline__ double wave_sum_p(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+__device__ __forceinline__ long long wave_min_p(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long u = __shfl_xor(v, o, 64);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
+// ---- tagged words: payload in the low 32 bits, iteration tag in the high 32
+typedef unsigned long long u64;
+template <typename T>
+struct Tag;
+template <>
+struct Tag<float> {
+    static constexpr int W = 1;
+    __device__ static void pack(float v, unsigned tag, u64 (&w)[1]) {
+        w[0] = (u64)__float_as_uint(v) | ((u64)tag << 32);
+    }
+    __device__ static float unpack(const u64 (&w)[1]) { return __uint_as_float((unsigned)w[0]); }
+};
+template <>
+struct Tag<double> {
+    static constexpr int W = 2;
+    __device__ static void pack(double v, unsigned tag, u64 (&w)[2]) {
+        const u64 bits = (u64)__double_as_longlong(v);
+        w[0] = (bits & 0xffffffffull) | ((u64)tag << 32);
+        w[1] = (bits >> 32) | ((u64)tag << 32);
+    }
+    __device__ static double unpack(const u64 (&w)[2]) {
+        return __longlong_as_double((long long)((w[0] & 0xffffffffull) | (w[1] << 32)));
+    }
+};
+template <int W>
+__device__ __forceinline__ bool tags_are(const u64 (&w)[W], unsigned tag) {
+    bool ok = true;
+#pragma unroll
+    for (int h = 0; h < W; ++h) ok &= (unsigned)(w[h] >> 32) == tag;
+    return ok;
+}
+template <int W>
+__device__ __forceinline__ void load_words(const u64* p, u64 (&w)[W]) {
+#pragma unroll
+    for (int h = 0; h < W; ++h) w[h] = ld_agent(p + h);
+}
+
+// A wait gives up after spin_limit polls, or early once another workgroup
+// has reported an error (checked every 1024 polls).
+__device__ __forceinline__ int wait_expired(long long spins, int* error, long long spin_limit) {
+    if (spins > spin_limit) return 1;
+    return (spins & 1023) == 0 && ld_agent(error) != 0;
+}
 
 constexpr int kCopyRegs = 8;
-constexpr int kBatch = 8;      // loads the reducer keeps in flight per thread
+constexpr int kBatch = 4;      // workgroups whose partials a reducer thread loads at once
 
-// Reducer workgroup: decision of every iteration from the published partials.
-template <int NT>
-__device__ void reducer_loop(const IterArgs<double>& ad, Ctrl* ctrl, const PersistArgs& p, int G,
-                             long long t0, double rho, double eps_rel, double* hist, int hist_cap) {
+// Position of this workgroup in the packing.  With xcd_remap, hardware
+// workgroup ids (dealt round-robin over the 8 XCDs) are renumbered so that
+// each XCD runs a contiguous range of the packing: neighbouring workgroups
+// then exchange their terms inside one XCD.
+__device__ __forceinline__ int logical_block(int bx, int nb, int remap) {
+    if (!remap) return bx;
+    const int x = bx & 7, j = bx >> 3;
+    const int full = nb >> 3, rem = nb & 7;
+    return x * full + (x < rem ? x : rem) + j;
+}
+
+// Everything one solve's persistent loop touches, for the single-instance
+// kernel and for each solve of the serving kernel.
+template <typename T>
+struct InstanceView {
+    const T* F;
+    const int2* winfo;
+    const int* var;
+    const int* meta;
+    const int* cstart;
+    const int* ccnt;
+    const int* clist;
+    const T* bbar;
+    const T* lo;
+    const T* hi;
+    const T* cost;
+    T* z0; T* z1;
+    T* l0; T* l1;
+    T* x0; T* x1;
+    u64* pub;
+    long long* flags;
+    double* partials;
+    long long* dec_iter;
+    long long* dec_stop;
+    Ctrl* ctrl;
+    double* hist;
+    int hist_cap;
+    int waves;
+    int check;
+    int lds_factors;
+    T rho, inv_rho;
+    double rho_d, eps_rel;
+    long long max_iter;
+    long long chunk;           // the launch ends for this solve after this many iterations
+};
+
+// Reducer workgroup of one solve: stop decisions of every iteration.  A
+// decision ends the launch for the solve when the test holds, on a NaN/Inf,
+// at max_iter, or after `chunk` iterations of this launch (a pause: the solve
+// continues in the next launch from the state written at the pause).
+template <typename T, int NT>
+__device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int* error, long long spin_limit) {
     __shared__ double rred[NT / 64][5];
+    __shared__ long long rmin[NT / 64];
     __shared__ int rstop;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    (void)ad;
-    long long t = t0;
+    Ctrl* ctrl = v.ctrl;
+    long long dec = t0;
+    long long spins = 0;
     for (;;) {
-        const long long tn = t + 1;
-        long long spins = 0;
-        for (;;) {
-            // up to kBatch flags per thread in flight at once
-            int mine = 1;
-            for (int q0 = threadIdx.x; q0 < G; q0 += kBatch * NT) {
-                long long f[kBatch];
-#pragma unroll
-                for (int k = 0; k < kBatch; ++k) {
-                    const int q = q0 + k * NT;
-                    f[k] = q < G ? ld_agent(&p.flags[q]) : tn;
-                }
-#pragma unroll
-                for (int k = 0; k < kBatch; ++k) mine &= (f[k] >= tn);
-            }
-            if (__syncthreads_and(mine)) break;
-            int bad = 0;
-            if (threadIdx.x == 0) bad = (ld_agent(p.error) != 0) || (++spins > p.spin_limit);
-            if (__syncthreads_or(bad)) {
-                if (threadIdx.x == 0) st_agent(p.error, (int)OPF_EHANG);
-                return;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-        const int par = (int)(tn & 1);
-        double acc5[5] = {0, 0, 0, 0, 0};
+        // ---- smallest iteration whose partials every workgroup has completed
+        long long fmin = 0x7fffffffffffffffll;
         for (int q0 = threadIdx.x; q0 < G; q0 += kBatch * NT) {
-            double v[kBatch][5];
+            long long f[kBatch];
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
                 const int q = q0 + k * NT;
-                const double* pp = p.partials + ((size_t)par * G + (q < G ? q : 0)) * 5;
-#pragma unroll
-                for (int i = 0; i < 5; ++i) v[k][i] = q < G ? ld_agent(&pp[i]) : 0.0;
+                f[k] = q < G ? ld_agent(&v.flags[q]) : 0x7fffffffffffffffll;
             }
-            // same summation order as a plain strided loop over q
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k)
-#pragma unroll
-                for (int i = 0; i < 5; ++i)
-                    if (q0 + k * NT < G) acc5[i] += v[k][i];
+            for (int k = 0; k < kBatch; ++k) fmin = f[k] < fmin ? f[k] : fmin;
         }
-#pragma unroll
-        for (int i = 0; i < 5; ++i) acc5[i] = wave_sum_p(acc5[i]);
-        if (lane == 0)
-#pragma unroll
-            for (int i = 0; i < 5; ++i) rred[wv][i] = acc5[i];
+        fmin = wave_min_p(fmin);
+        if (lane == 0) rmin[wv] = fmin;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double S[5] = {0, 0, 0, 0, 0};
-            for (int q = 0; q < NT / 64; ++q)
-#pragma unroll
-                for (int i = 0; i < 5; ++i) S[i] += rred[q][i];
-            const double pres = sqrt(S[0]);
-            const double dres = rho * sqrt(S[1]);
-            const double ep = eps_rel * fmax(sqrt(S[2]), sqrt(S[3]));
-            const double ed = eps_rel * sqrt(S[4]);
-            if (tn - 1 < hist_cap) {
-                hist[(tn - 1) * 4 + 0] = pres;
-                hist[(tn - 1) * 4 + 1] = dres;
-                hist[(tn - 1) * 4 + 2] = ep;
-                hist[(tn - 1) * 4 + 3] = ed;
+        fmin = rmin[0];
+        for (int q = 1; q < NT / 64; ++q) fmin = rmin[q] < fmin ? rmin[q] : fmin;
+        __syncthreads();
+        if (fmin <= dec) {
+            int bad = 0;
+            if (threadIdx.x == 0) bad = (ld_agent(error) != 0) || (++spins > spin_limit);
+            if (__syncthreads_or(bad)) {
+                if (threadIdx.x == 0) st_agent(error, (int)OPF_EHANG);
+                return;
             }
-            int stop = 0, status = OPF_OK;
-            if (!(isfinite(pres) && isfinite(dres) && isfinite(ep) && isfinite(ed))) {
-                stop = 1;
-                status = OPF_ENUMERIC;
-            } else if (p.check && pres <= ep && dres <= ed) {
-                stop = 1;
-            } else if (tn >= p.max_iter) {
-                stop = 1;
-                status = p.check ? OPF_NOT_CONVERGED : OPF_OK;
-            }
-            if (stop) {
-                // the final state is that of iteration tn (buffer tn & 1)
-                ctrl->iter = tn;
-                ctrl->status = status;
-                ctrl->res[0] = pres;
-                ctrl->res[1] = dres;
-                ctrl->res[2] = ep;
-                ctrl->res[3] = ed;
-                ctrl->stop = 1;
-            }
-            st_agent(&p.dec_stop[par], stop);
-            drain_memory();
-            st_agent(&p.dec_iter[par], tn);
-            rstop = stop;
+            __builtin_amdgcn_s_sleep(1);
+            continue;
         }
-        __syncthreads();
-        if (rstop) return;
-        t = tn;
+        spins = 0;
+        // ---- decide iterations dec+1 .. fmin in order (at most kDecisionLag)
+        for (long long u = dec + 1; u <= fmin; ++u) {
+            const int slot = (int)(u % kDecisionLag);
+            double acc5[5] = {0, 0, 0, 0, 0};
+            for (int q0 = threadIdx.x; q0 < G; q0 += kBatch * NT) {
+                double pv[kBatch][5];
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) {
+                    const int q = q0 + k * NT;
+                    const double* pp = v.partials + ((size_t)slot * G + (q < G ? q : 0)) * 5;
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) pv[k][i] = q < G ? ld_agent(&pp[i]) : 0.0;
+                }
+                // same summation order as a plain strided loop over q
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k)
+#pragma unroll
+                    for (int i = 0; i < 5; ++i)
+                        if (q0 + k * NT < G) acc5[i] += pv[k][i];
+            }
+#pragma unroll
+            for (int i = 0; i < 5; ++i) acc5[i] = wave_sum_p(acc5[i]);
+            if (lane == 0)
+#pragma unroll
+                for (int i = 0; i < 5; ++i) rred[wv][i] = acc5[i];
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double S[5] = {0, 0, 0, 0, 0};
+                for (int q = 0; q < NT / 64; ++q)
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) S[i] += rred[q][i];
+                const double pres = sqrt(S[0]);
+                const double dres = v.rho_d * sqrt(S[1]);
+                const double ep = v.eps_rel * fmax(sqrt(S[2]), sqrt(S[3]));
+                const double ed = v.eps_rel * sqrt(S[4]);
+                if (u - 1 < v.hist_cap) {
+                    v.hist[(u - 1) * 4 + 0] = pres;
+                    v.hist[(u - 1) * 4 + 1] = dres;
+                    v.hist[(u - 1) * 4 + 2] = ep;
+                    v.hist[(u - 1) * 4 + 3] = ed;
+                }
+                int end = 1, finished = 1, status = OPF_OK;
+                if (!(isfinite(pres) && isfinite(dres) && isfinite(ep) && isfinite(ed))) {
+                    status = OPF_ENUMERIC;
+                } else if (v.check && pres <= ep && dres <= ed) {
+                    status = OPF_OK;
+                } else if (u >= v.max_iter) {
+                    status = v.check ? OPF_NOT_CONVERGED : OPF_OK;
+                } else if (u >= t0 + v.chunk) {
+                    finished = 0;                      // pause
+                } else {
+                    end = 0;
+                }
+                if (end) {
+                    ctrl->iter = u;
+                    ctrl->status = status;
+                    ctrl->res[0] = pres;
+                    ctrl->res[1] = dres;
+                    ctrl->res[2] = ep;
+                    ctrl->res[3] = ed;
+                    ctrl->stop = finished;
+                    st_agent(v.dec_stop, u);
+                    drain_memory();          // the end iteration is visible before dec_iter reaches it
+                    st_agent(v.dec_iter, u);
+                }
+                rstop = end;
+            }
+            __syncthreads();
+            if (rstop) return;
+        }
+        if (threadIdx.x == 0) st_agent(v.dec_iter, fmin);
+        dec = fmin;
     }
 }
 
+// The persistent loop of one solve for workgroup b of its G compute
+// workgroups (b == G: its reducer).
 template <typename T, int WPB>
-__global__ __launch_bounds__(WPB * 64) void admm_persistent_kernel(IterArgs<T> a, PersistArgs p) {
+__device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int* error, long long spin_limit) {
     constexpr int NT = WPB * 64;
+    constexpr int W = Tag<T>::W;
+    constexpr int LAG = kDecisionLag;
     __shared__ T vsh[WPB][64];
     __shared__ double red[WPB][5];
     __shared__ int sh_flag;
 
-    const int G = (int)gridDim.x - 1;      // compute workgroups; the last one reduces
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int b = blockIdx.x;
     Ctrl* ctrl = a.ctrl;
     const long long t0 = ctrl->iter;
     if (b == G) {
-        IterArgs<double> dummy{};
-        reducer_loop<NT>(dummy, ctrl, p, G, t0, a.rho_d, a.eps_rel, a.hist, a.hist_cap);
+        reducer_loop<T, NT>(a, G, t0, error, spin_limit);
         return;
     }
     const int w = b * WPB + wv;
     const int d = w * 64 + lane;
+    const size_t LP = (size_t)a.waves * 64;
 
     // ---- static per-slot data, kept in registers
     const int g = a.var[d];
     const bool live = g >= 0;
     int meta = 0, cs = 0, cn = 1;
     int cp[kCopyRegs];
-    T bb = 0, lo = 0, hi = 0, cterm = 0;
+    T bb = 0, lo = 0, hi = 0, cost = 0;
     if (live) {
         meta = a.meta[d];
         cs = a.cstart[d];
@@ -192,11 +314,11 @@ __global__ __launch_bounds__(WPB * 64) void admm_persistent_kernel(IterArgs<T> a
         bb = a.bbar[d];
         lo = a.lo[d];
         hi = a.hi[d];
-        cterm = a.cost[d] * a.inv_rho;
+        cost = a.cost[d];
     }
     const int2 wi = a.winfo[w];
     const T* Fw = a.F + (size_t)wi.y * 64;
-    if (p.lds_factors) {
+    if (a.lds_factors) {
         // static factors of this workgroup's wavefronts, copied once into LDS
         extern __shared__ __align__(16) unsigned char dyn_lds[];
         T* Fl = reinterpret_cast<T*>(dyn_lds);
@@ -208,98 +330,132 @@ __global__ __launch_bounds__(WPB * 64) void admm_persistent_kernel(IterArgs<T> a
     }
     const int base = meta & 255;
     const bool owner = (meta >> 16) & 1;
-    // current local copy and dual of this slot (state of iteration t0)
-    T zc = 0, lc = 0;
+    const T inv_rho = a.inv_rho, rho = a.rho;
+    // state of the last LAG iterations: index 0 = current iteration t
+    T zh[LAG], lh[LAG], xh[LAG];
+#pragma unroll
+    for (int k = 0; k < LAG; ++k) zh[k] = lh[k] = xh[k] = 0;
     if (live) {
-        zc = (t0 & 1) ? a.z1[d] : a.z0[d];
-        lc = (t0 & 1) ? a.l1[d] : a.l0[d];
+        zh[0] = (t0 & 1) ? a.z1[d] : a.z0[d];
+        lh[0] = (t0 & 1) ? a.l1[d] : a.l0[d];
     }
-    const int nb0 = p.nbr_ptr[b], nbn = p.nbr_ptr[b + 1] - nb0;
 
     long long t = t0;
+    int bad = 0;
     for (;;) {
         const long long tn = t + 1;
-        // ---- thread 0: stop decision of iteration tn - 2 (published one
-        // iteration late); other threads: neighbours have published iteration t
+        long long spins = 0;            // polls of the waits of this iteration
+        // ---- thread 0: decision of iteration tn - LAG (issued first, checked after the gathers)
+        long long dseen = 0;
+        int errseen = 0;
         if (threadIdx.x == 0) {
-            int stop = 0;
-            if (tn - 2 > t0) {
-                const int slot = (int)((tn - 2) & 1);
-                long long spins = 0;
-                while (ld_agent(&p.dec_iter[slot]) != tn - 2) {
-                    if (ld_agent(p.error) != 0 || ++spins > p.spin_limit) {
-                        st_agent(p.error, (int)OPF_EHANG);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                stop = ld_agent(&p.dec_stop[slot]);
-            }
-            if (ld_agent(p.error) != 0) stop = 1;
-            sh_flag = stop;
-        } else {
-            for (int q = threadIdx.x - 1; q < nbn; q += NT - 1) {
-                const int nbk = p.nbr_list[nb0 + q];
-                long long spins = 0;
-                while (ld_agent(&p.flags[nbk]) < t) {
-                    if (ld_agent(p.error) != 0 || ++spins > p.spin_limit) {
-                        st_agent(p.error, (int)OPF_EHANG);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
+            dseen = ld_agent(a.dec_iter);
+            errseen = ld_agent(error);
         }
-        __syncthreads();
-        if (sh_flag) break;
-        // ---- global update for this slot's variable (all copies, fixed order)
-        const bool odd = (tn & 1) != 0;
-        const T* zp = odd ? a.z0 : a.z1;
-        const T* lp = odd ? a.l0 : a.l1;
-        T* zq = odd ? a.z1 : a.z0;
-        T* lq = odd ? a.l1 : a.l0;
-        T* xq = odd ? a.x1 : a.x0;
-        T xg = 0;
+        // ---- gather the terms of iteration t of every copy of this slot's variable
+        const unsigned tag = (unsigned)t;
+        const u64* pubr = a.pub + (size_t)(t & 1) * LP * W;
+        T acc = 0;
         if (live) {
-            T acc = 0;
+            u64 wd[kCopyRegs][W];
+#pragma unroll
+            for (int k = 0; k < kCopyRegs; ++k) {
+                if (k < cn && cp[k] != d) load_words<W>(pubr + (size_t)cp[k] * W, wd[k]);
+            }
 #pragma unroll
             for (int k = 0; k < kCopyRegs; ++k) {
                 if (k < cn) {
-                    const int e = cp[k];
-                    const T ze = (e == d) ? zc : ld_agent(&zp[e]);
-                    const T le = (e == d) ? lc : ld_agent(&lp[e]);
-                    acc += ze - le * a.inv_rho;
+                    T v;
+                    if (cp[k] == d) {
+                        v = copy_term(zh[0], lh[0], inv_rho);
+                    } else {
+                        while (!tags_are<W>(wd[k], tag) && !bad) {
+                            __builtin_amdgcn_s_sleep(1);
+                            load_words<W>(pubr + (size_t)cp[k] * W, wd[k]);
+                            bad = wait_expired(++spins, error, spin_limit);
+                        }
+                        v = Tag<T>::unpack(wd[k]);
+                    }
+                    acc += v;
                 }
             }
             for (int k = kCopyRegs; k < cn; ++k) {
                 const int e = a.clist[cs + k];
-                acc += ld_agent(&zp[e]) - ld_agent(&lp[e]) * a.inv_rho;
+                u64 we[W];
+                load_words<W>(pubr + (size_t)e * W, we);
+                while (!tags_are<W>(we, tag) && !bad) {
+                    __builtin_amdgcn_s_sleep(1);
+                    load_words<W>(pubr + (size_t)e * W, we);
+                    bad = wait_expired(++spins, error, spin_limit);
+                }
+                acc += Tag<T>::unpack(we);
             }
-            const T xh = (acc - cterm) / (T)cn;
-            xg = xh < lo ? lo : (xh > hi ? hi : xh);
         }
-        vsh[wv][lane] = live ? xg + lc * a.inv_rho : (T)0;
+        if (threadIdx.x == 0) {
+            // the gathers above waited for this thread's earlier stores too:
+            // the residual partials of iteration t are complete
+            drain_memory();
+            if (t > t0) st_agent(&a.flags[b], t);
+            while (dseen < tn - LAG && !bad && !errseen) {
+                __builtin_amdgcn_s_sleep(1);
+                dseen = ld_agent(a.dec_iter);
+                errseen = ld_agent(error);
+                if (++spins > spin_limit) bad = 1;
+            }
+            int stop = 0;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);   // dec_stop is read after dec_iter
+            if (!bad && !errseen && tn - LAG > t0) stop = ld_agent(a.dec_stop) == tn - LAG;
+            sh_flag = stop | (errseen ? 2 : 0);
+        }
+        if (__syncthreads_or(bad)) {
+            if (threadIdx.x == 0) st_agent(error, (int)OPF_EHANG);
+            break;
+        }
+        if (sh_flag) {
+            if (sh_flag == 1 && live) {
+                // state of the end iteration ts = tn - LAG = t - (LAG - 1)
+                const long long ts = tn - LAG;
+                T* zo = (ts & 1) ? a.z1 : a.z0;
+                T* lo_ = (ts & 1) ? a.l1 : a.l0;
+                T* xo = (ts & 1) ? a.x1 : a.x0;
+                zo[d] = zh[LAG - 1];
+                lo_[d] = lh[LAG - 1];
+                if (owner) xo[g] = xh[LAG - 1];
+            }
+            break;
+        }
+        // ---- global update, local projection, dual update, residual terms
+        T xg = 0;
+        if (live) xg = consensus_value(acc, cost, inv_rho, cn, lo, hi);
+        vsh[wv][lane] = live ? projection_input(xg, lh[0], inv_rho) : (T)0;
         __syncthreads();
-        // ---- local projection, dual update, residual terms
         double s[5] = {0, 0, 0, 0, 0};
         if (live) {
-            T acc = bb;
-            for (int k = 0; k < wi.x; ++k) acc += Fw[k * 64 + lane] * vsh[wv][(base + k) & 63];
-            const T zn = acc;
-            const T ln = lc + a.rho * (xg - zn);
-            st_agent(&zq[d], zn);
-            st_agent(&lq[d], ln);
-            if (owner) xq[g] = xg;
-            const double xd = (double)xg, zd = (double)zn;
+            T z = bb;
+            for (int k = 0; k < wi.x; ++k) z = fmadd(Fw[k * 64 + lane], vsh[wv][(base + k) & 63], z);
+            const T ln = dual_step(lh[0], rho, xg, z);
+            u64 wout[W];
+            Tag<T>::pack(copy_term(z, ln, inv_rho), (unsigned)tn, wout);
+            u64* pubw = a.pub + (size_t)(tn & 1) * LP * W + (size_t)d * W;
+#pragma unroll
+            for (int h = 0; h < W; ++h) st_agent(pubw + h, wout[h]);
+            const double xd = (double)xg, zd = (double)z;
             s[0] = (xd - zd) * (xd - zd);
-            s[1] = (zd - (double)zc) * (zd - (double)zc);
+            s[1] = (zd - (double)zh[0]) * (zd - (double)zh[0]);
             s[2] = xd * xd;
             s[3] = zd * zd;
             s[4] = (double)ln * (double)ln;
-            zc = zn;
-            lc = ln;
+#pragma unroll
+            for (int k = LAG - 1; k > 0; --k) {
+                zh[k] = zh[k - 1];
+                lh[k] = lh[k - 1];
+                xh[k] = xh[k - 1];
+            }
+            zh[0] = z;
+            lh[0] = ln;
+            xh[0] = xg;
         }
-        // ---- workgroup residual partial, then publish iteration tn
+        // ---- workgroup residual partial of iteration tn (flagged one iteration later)
 #pragma unroll
         for (int i = 0; i < 5; ++i) s[i] = wave_sum_p(s[i]);
         if (lane == 0)
@@ -311,37 +467,146 @@ __global__ __launch_bounds__(WPB * 64) void admm_persistent_kernel(IterArgs<T> a
             for (int q = 0; q < WPB; ++q)
 #pragma unroll
                 for (int i = 0; i < 5; ++i) bsum[i] += red[q][i];
-            double* pp = p.partials + ((size_t)(tn & 1) * G + b) * 5;
+            double* pp = a.partials + ((size_t)(tn % LAG) * G + b) * 5;
 #pragma unroll
             for (int i = 0; i < 5; ++i) st_agent(&pp[i], bsum[i]);
         }
-        drain_memory();          // this thread's z / lambda (and partial) stores are complete
-        __syncthreads();
-        if (threadIdx.x == 0) st_agent(&p.flags[b], tn);   // state and partials of tn are visible
         t = tn;
     }
 }
 
 template <typename T>
-__global__ void persistent_prepare_kernel(PersistArgs p, int G, Ctrl* ctrl) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const long long t0 = ctrl->iter;
-    if (i < G) p.flags[i] = t0;
-    if (i < 2) {
-        p.arrive[i] = 0u;
-        p.dec_iter[i] = -1;
-        p.dec_stop[i] = 0;
+__device__ __forceinline__ InstanceView<T> view_of(const IterArgs<T>& a, const PersistArgs& p) {
+    InstanceView<T> v;
+    v.F = a.F; v.winfo = a.winfo; v.var = a.var; v.meta = a.meta; v.cstart = a.cstart; v.ccnt = a.ccnt;
+    v.clist = a.clist; v.bbar = a.bbar; v.lo = a.lo; v.hi = a.hi; v.cost = a.cost;
+    v.z0 = a.z0; v.z1 = a.z1; v.l0 = a.l0; v.l1 = a.l1; v.x0 = a.x0; v.x1 = a.x1;
+    v.pub = p.pub; v.flags = p.flags; v.partials = p.partials; v.dec_iter = p.dec_iter; v.dec_stop = p.dec_stop;
+    v.ctrl = a.ctrl; v.hist = a.hist; v.hist_cap = a.hist_cap; v.waves = a.waves; v.check = p.check;
+    v.lds_factors = p.lds_factors; v.rho = a.rho; v.inv_rho = a.inv_rho; v.rho_d = a.rho_d;
+    v.eps_rel = a.eps_rel; v.max_iter = p.max_iter; v.chunk = 0x3fffffffffffffffll;
+    return v;
+}
+
+template <typename T, int WPB>
+__global__ __launch_bounds__(WPB * 64) void admm_persistent_kernel(IterArgs<T> a, PersistArgs p) {
+    const InstanceView<T> v = view_of(a, p);
+    const int b = logical_block((int)blockIdx.x, (int)gridDim.x, p.xcd_remap);
+    persistent_instance<T, WPB>(v, b, (int)gridDim.x - 1, p.error, p.spin_limit);
+}
+
+// Serving: the launch's workgroups are dealt to the resident solves by a work
+// list of (slot, workgroup of the solve; == blocks for its reducer).  Each
+// solve runs the single-instance persistent loop on its own state, for at
+// most `chunk` iterations, so every solve returns the same bits alone and in
+// any mix.
+__device__ __forceinline__ InstanceView<double> view_of(const InstDesc& D, const ServeArgs& s) {
+    InstanceView<double> v;
+    v.F = D.F; v.winfo = D.winfo; v.var = D.var; v.meta = D.meta; v.cstart = D.cstart; v.ccnt = D.ccnt;
+    v.clist = D.clist; v.bbar = D.bbar; v.lo = D.lo; v.hi = D.hi; v.cost = D.cost;
+    v.z0 = D.z0; v.z1 = D.z1; v.l0 = D.l0; v.l1 = D.l1; v.x0 = D.x0; v.x1 = D.x1;
+    v.pub = D.pub; v.flags = D.flags; v.partials = D.partials; v.dec_iter = D.dec; v.dec_stop = D.dec + 1;
+    v.ctrl = D.ctrl; v.hist = nullptr; v.hist_cap = 0; v.waves = D.lanes / 64; v.check = D.ctrl->check;
+    v.lds_factors = D.lds_factors; v.rho = D.rho; v.inv_rho = 1.0 / D.rho; v.rho_d = D.rho;
+    v.eps_rel = D.eps_rel; v.max_iter = D.ctrl->max_iter; v.chunk = s.chunk;
+    return v;
+}
+
+constexpr int kServeWPB = 4;
+
+__global__ __launch_bounds__(kServeWPB * 64) void admm_serve_kernel(const InstDesc* descs, const int2* work,
+                                                                     ServeArgs s) {
+    const int q = logical_block((int)blockIdx.x, (int)gridDim.x, s.xcd_remap);
+    const int2 wk = work[q];
+    const InstDesc& D = descs[wk.x];
+    if (D.ctrl->stop) return;               // finished solves stay resident until retired
+    const InstanceView<double> v = view_of(D, s);
+    persistent_instance<double, kServeWPB>(v, wk.y, D.blocks, s.error, s.spin_limit);
+}
+
+// Before a serving launch: each work item prepares its own part of its solve
+// (published terms of the start iteration, flags; the reducer item resets the
+// decisions); the first item clears the launch's error flag.
+__global__ void serve_prepare_kernel(const InstDesc* descs, const int2* work) {
+    const int2 wk = work[blockIdx.x];
+    const InstDesc& D = descs[wk.x];
+    const long long t0 = D.ctrl->iter;
+    const size_t LP = (size_t)D.lanes;
+    if (wk.y < D.blocks) {
+        const size_t d = (size_t)wk.y * blockDim.x + threadIdx.x;
+        const double z = (t0 & 1) ? D.z1[d] : D.z0[d];
+        const double l = (t0 & 1) ? D.l1[d] : D.l0[d];
+        u64 w[2];
+        Tag<double>::pack(copy_term(z, l, 1.0 / D.rho), (unsigned)t0, w);
+        for (int h = 0; h < 2; ++h) {
+            D.pub[d * 2 + h] = w[h];
+            D.pub[(LP + d) * 2 + h] = w[h];
+        }
+        if (threadIdx.x == 0) D.flags[wk.y] = t0;
+    } else if (threadIdx.x == 0) {
+        D.dec[0] = t0;
+        D.dec[1] = -1;
     }
+}
+
+__global__ void clear_flag_kernel(int* f) { *f = 0; }
+
+hipError_t launch_serve_persistent(const InstDesc* descs, const int2* work, int nwork, const ServeArgs& s,
+                                   hipStream_t st) {
+    if (nwork < 1) return hipSuccess;
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, st, s.error);
+    hipLaunchKernelGGL(serve_prepare_kernel, dim3(nwork), dim3(kServeWPB * 64), 0, st, descs, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ServeArgs sa = s;
+    void* args[] = {(void*)&descs, (void*)&work, (void*)&sa};
+    const size_t lds = (size_t)s.lds_cols * 64 * sizeof(double);
+    return hipLaunchCooperativeKernel((const void*)admm_serve_kernel, dim3(nwork), dim3(kServeWPB * 64), args, lds, st);
+}
+
+int serve_capacity(size_t lds_bytes) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_serve_kernel, kServeWPB * 64, lds_bytes) != hipSuccess)
+        return 0;
+    return per * cus;
+}
+
+// Before a launch: the published terms of the start iteration t0 (both parity
+// buffers, tag t0; the other buffer's tag t0 never matches a later
+// iteration), reducer flags and decisions at t0, error cleared.
+template <typename T>
+__global__ void persistent_prepare_kernel(IterArgs<T> a, PersistArgs p, int G) {
+    constexpr int W = Tag<T>::W;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t0 = a.ctrl->iter;
+    const size_t LP = (size_t)a.waves * 64;
+    if ((size_t)i < LP) {
+        const T z = (t0 & 1) ? a.z1[i] : a.z0[i];
+        const T l = (t0 & 1) ? a.l1[i] : a.l0[i];
+        u64 w[W];
+        Tag<T>::pack(copy_term(z, l, a.inv_rho), (unsigned)t0, w);
+#pragma unroll
+        for (int h = 0; h < W; ++h) {
+            p.pub[(size_t)i * W + h] = w[h];
+            p.pub[(LP + i) * W + h] = w[h];
+        }
+    }
+    if (i < G) p.flags[i] = t0;
     if (i == 0) {
+        *p.dec_iter = t0;
+        *p.dec_stop = -1;
         *p.error = 0;
-        *p.stopped = 0;
     }
 }
 
 template <typename T>
 hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G, hipStream_t st) {
     const size_t lds = p.lds_factors ? (size_t)p.lds_factor_cols * 64 * sizeof(T) : 0;
-    hipLaunchKernelGGL((persistent_prepare_kernel<T>), dim3((G + 255) / 256), dim3(256), 0, st, p, G, a.ctrl);
+    const size_t LP = (size_t)a.waves * 64;
+    const int n = (int)std::max<size_t>(LP, (size_t)G);
+    hipLaunchKernelGGL((persistent_prepare_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, a, p, G);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     void* args[] = {(void*)&a, (void*)&p};

@@ -18,11 +18,6 @@
 
 namespace opf {
 
-template <typename T>
-__device__ __forceinline__ T clampv(T v, T lo, T hi) {
-    return v < lo ? lo : (v > hi ? hi : v);
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -143,14 +138,13 @@ __global__ __launch_bounds__(WPB * 64) void admm_step_kernel(IterArgs<T> a) {
             T acc = 0;
             for (int k = 0; k < cn; ++k) {
                 const int e = a.clist[cs + k];
-                acc += zp[e] - lp[e] * a.inv_rho;
+                acc += copy_term(zp[e], lp[e], a.inv_rho);
             }
-            const T xh = (acc - a.cost[d] * a.inv_rho) / (T)cn;
-            xg = clampv(xh, a.lo[d], a.hi[d]);
+            xg = consensus_value(acc, a.cost[d], a.inv_rho, cn, a.lo[d], a.hi[d]);
             zold = zp[d];
             lold = lp[d];
         }
-        vsh[wv][lane] = (g >= 0) ? xg + lold * a.inv_rho : (T)0;
+        vsh[wv][lane] = (g >= 0) ? projection_input(xg, lold, a.inv_rho) : (T)0;
     }
     __syncthreads();
     double s[5] = {0, 0, 0, 0, 0};
@@ -159,9 +153,9 @@ __global__ __launch_bounds__(WPB * 64) void admm_step_kernel(IterArgs<T> a) {
         const T* Fw = a.F + (size_t)wi.y * 64;
         const int base = meta & 255;
         T acc = a.bbar[d];
-        for (int k = 0; k < wi.x; ++k) acc += Fw[k * 64 + lane] * vsh[wv][(base + k) & 63];
+        for (int k = 0; k < wi.x; ++k) acc = fmadd(Fw[k * 64 + lane], vsh[wv][(base + k) & 63], acc);
         const T zn = acc;
-        const T ln = lold + a.rho * (xg - zn);
+        const T ln = dual_step(lold, a.rho, xg, zn);
         zq[d] = zn;
         lq[d] = ln;
         if (meta & (1 << 16)) xq[g] = xg;

@@ -106,14 +106,12 @@ struct opf_admm_handle {
     // persistent schedule
     int kernel = OPF_KERNEL_STEP;
     int capacity = 0;
-    int* nbr_ptr = nullptr;
-    int* nbr_list = nullptr;
+    unsigned long long* pub = nullptr;   // published copy terms [2][LP][2] (tagged words)
     long long* flags = nullptr;
-    unsigned* arrive = nullptr;
     long long* dec_iter = nullptr;
-    int* dec_stop = nullptr;
+    long long* dec_stop = nullptr;
     int* dev_error = nullptr;
-    int* stopped = nullptr;
+    int xcd_remap = 1;
     int* error_host = nullptr;     // pinned
     int lds_cols = 0;              // factor columns of the largest workgroup
     int lds32 = 0, lds64 = 0;      // factors resident in LDS for each precision
@@ -269,15 +267,13 @@ template <typename T>
 int run_phase_persistent(opf_admm_handle* h, PrecState<T>& s, long long max_iter, int check) {
     IterArgs<T> a = iter_args(h, s);
     PersistArgs p;
-    p.nbr_ptr = h->nbr_ptr;
-    p.nbr_list = h->nbr_list;
+    p.pub = h->pub;
     p.flags = h->flags;
-    p.arrive = h->arrive;
     p.partials = h->partials;
     p.dec_iter = h->dec_iter;
     p.dec_stop = h->dec_stop;
     p.error = h->dev_error;
-    p.stopped = h->stopped;
+    p.xcd_remap = h->xcd_remap;
     p.spin_limit = h->opt.spin_limit > 0 ? h->opt.spin_limit : 4000000LL;
     p.max_iter = max_iter;
     p.check = check;
@@ -514,6 +510,7 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     }
     h->LP = h->lay.waves * kWave;
     h->user_stream = (hipStream_t)hip_stream;
+    h->xcd_remap = opt.workgroup_order == 1 ? 0 : 1;
     h->wpb = h->lay.block_waves;
     auto fail = [&](int code) {
         std::string m = h->err;
@@ -551,15 +548,14 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     if ((rc = dalloc(h, &h->xo, L.n))) return fail(rc);
     const int blocks = L.blocks;
     h->grid_blocks = blocks;
-    if ((rc = dalloc(h, &h->partials, (size_t)blocks * 10 + 10))) return fail(rc);
-    if ((rc = upload(h, &h->nbr_ptr, L.nbr_ptr))) return fail(rc);
-    if ((rc = upload(h, &h->nbr_list, L.nbr_list))) return fail(rc);
+    // residual partials: one slot per workgroup for the step kernel, a ring of
+    // kDecisionLag slots per workgroup for the persistent kernel
+    if ((rc = dalloc(h, &h->partials, (size_t)blocks * 5 * kDecisionLag + 10))) return fail(rc);
+    if ((rc = dalloc(h, &h->pub, (size_t)h->LP * 4))) return fail(rc);
     if ((rc = dalloc(h, &h->flags, blocks))) return fail(rc);
-    if ((rc = dalloc(h, &h->arrive, 2))) return fail(rc);
-    if ((rc = dalloc(h, &h->dec_iter, 2))) return fail(rc);
-    if ((rc = dalloc(h, &h->dec_stop, 2))) return fail(rc);
+    if ((rc = dalloc(h, &h->dec_iter, 1))) return fail(rc);
+    if ((rc = dalloc(h, &h->dec_stop, 1))) return fail(rc);
     if ((rc = dalloc(h, &h->dev_error, 1))) return fail(rc);
-    if ((rc = dalloc(h, &h->stopped, 1))) return fail(rc);
     if (hipHostMalloc((void**)&h->error_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return fail(set_err(h, OPF_ENOMEM, "hipHostMalloc failed"));
     *h->error_host = 0;

@@ -2,9 +2,10 @@
 //
 // Threads: set-up workers (validation, row reduction, factors, packing of a
 // submitted problem into a contiguous device image) and one GPU worker that
-// admits ready solves into the device arena while their footprint fits,
-// replays a captured graph of shared iteration launches, polls the per-solve
-// stop flags, and retires finished solves (outputs, warm-start state).
+// admits ready solves into the device arena while their footprint (HBM) and
+// their workgroups (co-resident capacity) fit, runs all resident solves in one
+// persistent launch for a chunk of iterations each, polls the per-solve stop
+// flags, and retires finished solves (outputs, warm-start state).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +33,7 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 constexpr int kWPB = 4;              // wavefronts per workgroup of the shared launch
+constexpr int kServeLdsCols = 96;    // factor columns per workgroup held in LDS (48 KiB in FP64)
 constexpr size_t kAlign = 256;
 
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -39,7 +41,7 @@ size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Offsets of the arrays of one resident solve inside its arena region.
 struct Image {
     size_t winfo, var, meta, cstart, ccnt, clist, user_slot, F, bbar, lo, hi, cost, zdef, zdef_user;
-    size_t z0, z1, l0, l1, x0, x1, partials, zu, lu, xo, plan, total;
+    size_t z0, z1, l0, l1, x0, x1, partials, pub, flags, dec, zu, lu, xo, plan, total;
 };
 
 struct Request {
@@ -57,6 +59,7 @@ struct Request {
     Image img{};
     std::vector<unsigned char> bytes;       // static part of the region image
     std::vector<int32_t> comp_off;          // user-order offset of each component
+    int lds_ok = 0;                         // every workgroup's factors fit the LDS budget
     clk::time_point t_submit, t_admit;
 };
 
@@ -140,7 +143,10 @@ Image plan_image(const HostLayout& L) {
     im.l1 = take(8 * LP);
     im.x0 = take(8 * (size_t)L.n);
     im.x1 = take(8 * (size_t)L.n);
-    im.partials = take(8 * 5 * (size_t)L.blocks);
+    im.partials = take(8 * 5 * (size_t)L.blocks * kDecisionLag);
+    im.pub = take(8 * 2 * 2 * LP);
+    im.flags = take(8 * (size_t)L.blocks);
+    im.dec = take(16);
     im.zu = take(8 * (size_t)L.L);
     im.lu = take(8 * (size_t)L.L);
     im.xo = take(8 * (size_t)L.n);
@@ -165,14 +171,15 @@ struct opf_server {
     Arena arena;
     InstDesc* d_descs = nullptr;
     int2* d_work = nullptr;
-    int* d_nwork = nullptr;
     Ctrl* d_ctrls = nullptr;
     Ctrl* h_ctrls = nullptr;
     int2* h_work = nullptr;
-    int* h_nwork = nullptr;
-    std::map<int, hipGraphExec_t> graphs;  // grid size -> graph of iters_per_poll shared launches
+    int nwork = 0;
+    int* d_error = nullptr;
+    int* h_error = nullptr;
+    int capacity = 0;                      // co-resident workgroups of the serving kernel
     std::vector<Slot> slots;
-    int active = 0, active_blocks = 0;
+    int active = 0, active_blocks = 0;     // resident solves, their workgroups (reducers included)
     bool dirty = true;
     std::mutex mu;
     std::condition_variable cv_setup, cv_work, cv_result;
@@ -279,6 +286,13 @@ void setup_loop(opf_server* s) {
                 for (size_t d = 0; d < L.user_slot.size(); ++d)
                     if (L.user_slot[d] >= 0) zu[L.user_slot[d]] = L.z0[d];
                 put(r->bytes, im.zdef_user, zu);
+                int cols = 0;
+                for (int b = 0; b < L.blocks; ++b) {
+                    int c = 0;
+                    for (int q = 0; q < kWPB; ++q) c += L.wave_maxn[(size_t)b * kWPB + q];
+                    cols = std::max(cols, c);
+                }
+                r->lds_ok = cols <= kServeLdsCols;
                 r->comp_off.assign(r->S, 0);
                 for (int q = 1; q < r->S; ++q) r->comp_off[q] = r->comp_off[q - 1] + r->cn[q - 1];
             }
@@ -356,6 +370,10 @@ int admit_one(opf_server* s, std::unique_ptr<Request>& r, int slot_id) {
     D.x0 = reinterpret_cast<double*>(base + im.x0);
     D.x1 = reinterpret_cast<double*>(base + im.x1);
     D.partials = reinterpret_cast<double*>(base + im.partials);
+    D.pub = reinterpret_cast<unsigned long long*>(base + im.pub);
+    D.flags = reinterpret_cast<long long*>(base + im.flags);
+    D.dec = reinterpret_cast<long long*>(base + im.dec);
+    D.lds_factors = q.lds_ok;
     D.ctrl = s->d_ctrls + slot_id;
     D.blocks = L.blocks;
     D.lanes = L.waves * kWave;
@@ -398,7 +416,7 @@ int admit_one(opf_server* s, std::unique_ptr<Request>& r, int slot_id) {
     q.t_admit = clk::now();
     sl.req = std::move(r);
     s->active++;
-    s->active_blocks += L.blocks;
+    s->active_blocks += L.blocks + 1;
     s->dirty = true;
     return 1;
 }
@@ -413,8 +431,14 @@ bool admit_ready(opf_server* s) {
         int free_slot = -1;
         for (int q = 0; q < (int)s->slots.size(); ++q)
             if (!s->slots[q].used) { free_slot = q; break; }
+        const int need = r->lay.blocks + 1;        // compute workgroups + reducer
+        const int limit = std::min(s->opt.max_workgroups, s->capacity);
+        if (need > limit) {
+            push_result(s, *r, OPF_ENOMEM, nullptr, 0);   // can never be co-resident on this device
+            continue;
+        }
         int rc = 0;
-        if (free_slot >= 0 && s->active_blocks + r->lay.blocks <= s->opt.max_workgroups)
+        if (free_slot >= 0 && s->active_blocks + need <= limit)
             rc = admit_one(s, r, free_slot);
         if (rc < 0) {
             push_result(s, *r, OPF_EHIP, nullptr, 0);   // device failure: report and drop
@@ -474,34 +498,20 @@ bool retire(opf_server* s, int slot_id) {
     push_result(s, q, c.status, &c, sl.warm);
     s->arena.release(sl.off, sl.len);
     s->active--;
-    s->active_blocks -= L.blocks;
+    s->active_blocks -= L.blocks + 1;
     sl.used = false;
     sl.req.reset();
     s->dirty = true;
     return true;
 }
 
-// Graph of `iters_per_poll` shared launches over a grid of `grid` workgroups
-// (grids come in powers of two so that few graphs cover every mix).
-hipGraphExec_t graph_for(opf_server* s, int grid) {
-    auto it = s->graphs.find(grid);
-    if (it != s->graphs.end()) return it->second;
-    hipGraph_t g = nullptr;
-    hipGraphExec_t ge = nullptr;
-    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-    bool ok = true;
-    for (int i = 0; i < s->opt.iters_per_poll && ok; ++i)
-        ok = launch_multi_step(s->d_descs, s->d_work, s->d_nwork, grid, kWPB, s->stream) == hipSuccess;
-    if (hipStreamEndCapture(s->stream, &g) != hipSuccess) ok = false;
-    if (ok && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) ok = false;
-    if (g) (void)hipGraphDestroy(g);
-    if (!ok) return nullptr;
-    s->graphs[grid] = ge;
-    return ge;
-}
-
 void worker_loop(opf_server* s) {
-    const int k = std::max(1, s->opt.iters_per_poll);
+    ServeArgs sa{};
+    sa.error = s->d_error;
+    sa.spin_limit = s->opt.admm.spin_limit > 0 ? s->opt.admm.spin_limit : 4000000LL;
+    sa.chunk = std::max(1, s->opt.iters_per_poll);
+    sa.xcd_remap = s->opt.admm.workgroup_order == 1 ? 0 : 1;
+    sa.lds_cols = kServeLdsCols;
     for (;;) {
         if (s->quit.load()) return;
         admit_ready(s);
@@ -515,37 +525,34 @@ void worker_loop(opf_server* s) {
             int nw = 0;
             for (int q = 0; q < (int)s->slots.size(); ++q) {
                 if (!s->slots[q].used) continue;
-                for (int b = 0; b < s->slots[q].desc.blocks; ++b) s->h_work[nw++] = make_int2(q, b);
+                for (int b = 0; b <= s->slots[q].desc.blocks; ++b) s->h_work[nw++] = make_int2(q, b);
             }
-            *s->h_nwork = nw;
-            if (hipMemcpyAsync(s->d_work, s->h_work, sizeof(int2) * std::max(nw, 1), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-                hipMemcpyAsync(s->d_nwork, s->h_nwork, sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess) {
+            s->nwork = nw;
+            if (hipMemcpyAsync(s->d_work, s->h_work, sizeof(int2) * std::max(nw, 1), hipMemcpyHostToDevice,
+                               s->stream) != hipSuccess) {
                 serr(s, OPF_EHIP, "work list upload failed");
                 return;
             }
             s->dirty = false;
         }
-        int grid = 64;
-        while (grid < *s->h_nwork) grid *= 2;
-        grid = std::min(grid, s->opt.max_workgroups);
-        hipGraphExec_t graph = graph_for(s, grid);
-        if (!graph) {
-            serr(s, OPF_EHIP, "graph capture failed");
-            return;
-        }
         const auto t0 = clk::now();
-        if (hipGraphLaunch(graph, s->stream) != hipSuccess ||
+        if (launch_serve_persistent(s->d_descs, s->d_work, s->nwork, sa, s->stream) != hipSuccess ||
             hipMemcpyAsync(s->h_ctrls, s->d_ctrls, sizeof(Ctrl) * s->slots.size(), hipMemcpyDeviceToHost,
                            s->stream) != hipSuccess ||
+            hipMemcpyAsync(s->h_error, s->d_error, sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
             hipStreamSynchronize(s->stream) != hipSuccess) {
             serr(s, OPF_EHIP, "shared iteration launch failed");
             return;
         }
         s->busy_ms += ms_since(t0, clk::now());
-        s->launches += k;
-        for (int q = 0; q < (int)s->slots.size(); ++q)
-            if (s->slots[q].used && s->h_ctrls[q].stop)
+        s->launches += 1;
+        const bool hang = *s->h_error != 0;
+        for (int q = 0; q < (int)s->slots.size(); ++q) {
+            if (!s->slots[q].used) continue;
+            if (hang) s->h_ctrls[q].status = OPF_EHANG;     // a bounded wait ran out: end every resident solve
+            if (hang || s->h_ctrls[q].stop)
                 if (!retire(s, q)) return;
+        }
     }
 }
 
@@ -561,7 +568,7 @@ void opf_server_default_options(opf_server_options* o) {
     o->warm_bytes = (int64_t)1 << 30;
     o->max_slots = 256;
     o->max_workgroups = 8192;
-    o->iters_per_poll = 64;
+    o->iters_per_poll = 256;
     o->setup_threads = 4;
     o->warm_start = 1;
 }
@@ -594,18 +601,20 @@ int opf_server_create(const opf_server_options* o, void* hip_stream, opf_server*
     const int MS = opt.max_slots, MW = opt.max_workgroups;
     if (hipMalloc((void**)&s->d_descs, sizeof(InstDesc) * MS) != hipSuccess ||
         hipMalloc((void**)&s->d_work, sizeof(int2) * MW) != hipSuccess ||
-        hipMalloc((void**)&s->d_nwork, sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&s->d_error, sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&s->d_ctrls, sizeof(Ctrl) * MS) != hipSuccess)
         return fail(OPF_ENOMEM, "device allocation failed");
     if (hipHostMalloc((void**)&s->h_ctrls, sizeof(Ctrl) * MS, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&s->h_work, sizeof(int2) * MW, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&s->h_nwork, sizeof(int), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void**)&s->h_error, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return fail(OPF_ENOMEM, "pinned allocation failed");
-    *s->h_nwork = 0;
-    if (hipMemsetAsync(s->d_nwork, 0, sizeof(int), s->stream) != hipSuccess ||
+    *s->h_error = 0;
+    if (hipMemsetAsync(s->d_error, 0, sizeof(int), s->stream) != hipSuccess ||
         hipMemsetAsync(s->d_ctrls, 0, sizeof(Ctrl) * MS, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return fail(OPF_EHIP, "device initialisation failed");
+    s->capacity = serve_capacity((size_t)kServeLdsCols * 64 * sizeof(double));
+    if (s->capacity < 2) return fail(OPF_EHIP, "the serving kernel cannot be resident on this device");
     s->slots.resize(MS);
     opf_server* raw = s.release();
     for (int t = 0; t < raw->opt.setup_threads; ++t) raw->setup_threads.emplace_back(setup_loop, raw);
@@ -698,15 +707,14 @@ void opf_server_destroy(opf_server* s) {
         (void)hipFree(w.second.z);
         (void)hipFree(w.second.l);
     }
-    for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.second);
     if (s->arena_base) (void)hipFree(s->arena_base);
     if (s->d_descs) (void)hipFree(s->d_descs);
     if (s->d_work) (void)hipFree(s->d_work);
-    if (s->d_nwork) (void)hipFree(s->d_nwork);
+    if (s->d_error) (void)hipFree(s->d_error);
     if (s->d_ctrls) (void)hipFree(s->d_ctrls);
     if (s->h_ctrls) (void)hipHostFree(s->h_ctrls);
     if (s->h_work) (void)hipHostFree(s->h_work);
-    if (s->h_nwork) (void)hipHostFree(s->h_nwork);
+    if (s->h_error) (void)hipHostFree(s->h_error);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
