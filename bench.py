@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--kernel", default="auto", choices=["auto", "step", "persistent"])
     ap.add_argument("--block-waves", type=int, default=0)
     ap.add_argument("--workgroup-order", type=int, default=0, choices=[0, 1],
-                    help="persistent kernel: 0 = XCD-contiguous packing ranges, 1 = hardware order")
+                    help="persistent kernel: 0 = hardware workgroup order, 1 = XCD-contiguous packing ranges")
     ap.add_argument("--check-every", type=int, default=1024)
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="time this many iterations per step instead of solving to tolerance")

@@ -115,9 +115,13 @@ typedef struct opf_admm_options {
     int32_t autotune;       /* 1: with kernel AUTO and block_waves 0, time short runs of each
                                schedule and workgroup shape on this problem and keep the fastest
                                (decisions cached per problem shape for the process) */
-    int32_t workgroup_order; /* PERSISTENT: 0 = each XCD runs a contiguous range of the packed
-                               workgroups (neighbours share an L2), 1 = hardware order */
-    int32_t reserved[3];
+    int32_t workgroup_order; /* PERSISTENT: 0 = hardware order of workgroups (default; measured
+                               faster), 1 = each XCD runs a contiguous range of the packing */
+    int32_t setup_on_device; /* 1: row reduction and factors of every component run on the GPU
+                               (Section IV-B, closed_2; one workgroup per component) instead of
+                               host threads; same results to rounding; components needing more
+                               than 64 KiB of LDS make the set-up fail with OPF_EINVAL */
+    int32_t reserved[2];
 } opf_admm_options;
 
 /* Optional warm start: z0 and lambda0 in user slot order (length L). */

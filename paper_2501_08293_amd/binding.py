@@ -55,7 +55,7 @@ class opf_admm_options(C.Structure):
                 ("precision", C.c_int32), ("polish", C.c_int32), ("check_every", C.c_int32),
                 ("kernel", C.c_int32), ("history_cap", C.c_int32), ("block_waves", C.c_int32),
                 ("spin_limit", C.c_int32), ("split_terms", C.c_int32), ("autotune", C.c_int32),
-                ("workgroup_order", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("workgroup_order", C.c_int32), ("setup_on_device", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class opf_warm(C.Structure):
@@ -356,7 +356,7 @@ class Solver:
     def __init__(self, n, c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx, *, rho=100.0,
                  eps_rel=1e-3, max_iter=1_000_000, precision=OPF_PREC_FP64, polish=True, check_every=256,
                  kernel=OPF_KERNEL_AUTO, history_cap=0, block_waves=0, spin_limit=0, autotune=False,
-                 workgroup_order=0, stream=0):
+                 workgroup_order=0, setup_on_device=False, stream=0):
         self._keep = dict(
             c=np.ascontiguousarray(c, np.float64), lb=np.ascontiguousarray(lb, np.float64),
             ub=np.ascontiguousarray(ub, np.float64), var_kind=np.ascontiguousarray(var_kind, np.uint8),
@@ -384,6 +384,7 @@ class Solver:
         o.spin_limit = spin_limit
         o.autotune = int(bool(autotune))
         o.workgroup_order = workgroup_order
+        o.setup_on_device = int(bool(setup_on_device))
         self.options = o
         self.h = opf_admm_setup(p, o, stream)
         self._keep = None   # the library copied everything it needs

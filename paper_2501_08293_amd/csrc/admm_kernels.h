@@ -30,6 +30,25 @@ template <typename T>
 __device__ __forceinline__ T projection_input(T x, T l, T inv_rho) {
     return fmadd(l, inv_rho, x);
 }
+// local projection closed_2 for one slot: acc + sum_k F[k][lane] v[(base + k) & 63]
+// over k ascending (F column-blocked [k][lane]); the loads of eight columns are
+// issued ahead of their dependent fused multiply-adds
+template <typename T>
+__device__ __forceinline__ T project_row(const T* F, const T* v, int base, int lane, int ncols, T acc) {
+    int k = 0;
+    for (; k + 8 <= ncols; k += 8) {
+        T f[8], x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            f[j] = F[(k + j) * 64 + lane];
+            x[j] = v[(base + k + j) & 63];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc = fmadd(f[j], x[j], acc);
+    }
+    for (; k < ncols; ++k) acc = fmadd(F[k * 64 + lane], v[(base + k) & 63], acc);
+    return acc;
+}
 // dual update ADMM-3: lambda_s + rho (B_s x - x_s)
 template <typename T>
 __device__ __forceinline__ T dual_step(T l, T rho, T x, T z) {
@@ -81,8 +100,7 @@ struct IterArgs {
 // Extra state of the persistent kernel (see admm_persistent.hip).
 struct PersistArgs {
     unsigned long long* pub;    // [2][LP][words] published copy terms with iteration tags
-    long long* flags;           // [G] iteration whose residual partials each workgroup has completed
-    double* partials;           // [kDecisionLag][G][5] residual partial sums
+    unsigned long long* records;// [kDecisionLag][10][G] tagged residual partial sums (word-major)
     long long* dec_iter;        // last iteration the reducer has decided
     long long* dec_stop;        // stop iteration, -1 while running
     int* error;                 // OPF_EHANG when a bounded wait ran out
@@ -116,9 +134,8 @@ struct InstDesc {
     double* z0; double* z1;
     double* l0; double* l1;
     double* x0; double* x1;
-    double* partials;           // [kDecisionLag][blocks][5]
+    unsigned long long* records;// [kDecisionLag][10][blocks] tagged residual partial sums (word-major)
     unsigned long long* pub;    // [2][lanes][2] published copy terms (persistent schedule)
-    long long* flags;           // [blocks]
     long long* dec;             // [2]: last decided iteration, stop iteration
     Ctrl* ctrl;
     int blocks;                 // workgroups of this solve
@@ -149,6 +166,25 @@ hipError_t launch_warm_gather(const int4* plan, int nplan, const double* rz, con
                               double* lu, hipStream_t st);
 hipError_t launch_to_device_order(const double* zu, const double* lu, const int* user_slot, int lanes,
                                   const double* zdef, double* zd, double* ld, int use_warm, hipStream_t st);
+
+// ---- device set-up of the component factors (see setup_device.hip)
+struct FactorJob {
+    const double* A;          // concatenated row-major m_s x n_s blocks
+    const double* b;          // concatenated m_s entries
+    const int64_t* aoff;      // [S]
+    const int64_t* boff;      // [S]
+    const int* comp_m;        // [S]
+    const int* comp_n;        // [S]
+    const int* comp_dev;      // [S] first device slot of the component
+    const int64_t* wave_foff; // [waves] element offset of each wave's factor block
+    double* F;                // packed factors (zeroed before the launch)
+    double* bbar;             // [lanes]
+    int* status;              // [S] 0 or OPF_EINFEASIBLE_COMPONENT
+    int S;
+};
+size_t factor_lds_bytes(int m, int n);
+hipError_t launch_factors(const FactorJob& job, size_t lds_bytes, hipStream_t st);
+hipError_t launch_narrow(const double* src, float* dst, int64_t count, hipStream_t st);
 
 // ---- batched same-topology scenarios (see admm_batch.hip)
 struct BatchCtrl {

@@ -15,12 +15,12 @@
 // term of t, which each neighbour computed after reading the old term of
 // t - 1 that t + 1 overwrites.
 //
-// Termination: each workgroup writes its FP64 residual partial sums of
-// iteration t into a ring of kDecisionLag slots and, one iteration later
-// (after the wait for its gathers has also completed those stores), an
-// iteration flag.  One extra workgroup (the reducer, last of the grid) waits
-// for every flag, reduces the partials in a fixed order and publishes the last
-// decided iteration and, on a stop, the stop iteration ts.  A workgroup acts
+// Termination: each workgroup writes its five FP64 residual partial sums of
+// iteration t, split into tagged 64-bit words like the copy terms, into a ring
+// of kDecisionLag records.  One extra workgroup (the reducer, last of the
+// grid) polls the records of iteration t until every tag is t, reduces them in
+// a fixed order and publishes the last decided iteration and, on a stop, the
+// stop iteration ts.  A workgroup acts
 // on the decision of iteration tn - kDecisionLag at the start of tn, so every
 // workgroup computes exactly the iterations up to ts + kDecisionLag - 1 (no
 // wait can outlive its producer), and keeps the state of its last
@@ -111,7 +111,8 @@ __device__ __forceinline__ int wait_expired(long long spins, int* error, long lo
 }
 
 constexpr int kCopyRegs = 8;
-constexpr int kBatch = 4;      // workgroups whose partials a reducer thread loads at once
+constexpr int kBatch = 3;      // workgroups whose records a reducer thread loads at once
+constexpr int kRec = 10;       // words of one residual record (5 doubles, two tagged halves each)
 
 // Position of this workgroup in the packing.  With xcd_remap, hardware
 // workgroup ids (dealt round-robin over the 8 XCDs) are renumbered so that
@@ -143,8 +144,7 @@ struct InstanceView {
     T* l0; T* l1;
     T* x0; T* x1;
     u64* pub;
-    long long* flags;
-    double* partials;
+    u64* records;
     long long* dec_iter;
     long long* dec_stop;
     Ctrl* ctrl;
@@ -166,114 +166,108 @@ struct InstanceView {
 template <typename T, int NT>
 __device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int* error, long long spin_limit) {
     __shared__ double rred[NT / 64][5];
-    __shared__ long long rmin[NT / 64];
     __shared__ int rstop;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     Ctrl* ctrl = v.ctrl;
-    long long dec = t0;
-    long long spins = 0;
-    for (;;) {
-        // ---- smallest iteration whose partials every workgroup has completed
-        long long fmin = 0x7fffffffffffffffll;
+    for (long long u = t0 + 1;; ++u) {
+        // ---- records of iteration u of every workgroup, summed in a fixed order
+        // (per thread over q = tid, tid + NT, ..., then across lanes and waves)
+        const unsigned tag = (unsigned)u;
+        // word w of workgroup q at rec[w * G + q]: one load instruction per
+        // word covers 64 consecutive workgroups
+        const u64* rec = v.records + (size_t)(u % kDecisionLag) * G * kRec;
+        double acc5[5] = {0, 0, 0, 0, 0};
+        int bad = 0;
+        long long spins = 0;
         for (int q0 = threadIdx.x; q0 < G; q0 += kBatch * NT) {
-            long long f[kBatch];
+            u64 wd[kBatch][kRec];
+            unsigned pending = 0;
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
                 const int q = q0 + k * NT;
-                f[k] = q < G ? ld_agent(&v.flags[q]) : 0x7fffffffffffffffll;
-            }
+                if (q < G) {
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k) fmin = f[k] < fmin ? f[k] : fmin;
-        }
-        fmin = wave_min_p(fmin);
-        if (lane == 0) rmin[wv] = fmin;
-        __syncthreads();
-        fmin = rmin[0];
-        for (int q = 1; q < NT / 64; ++q) fmin = rmin[q] < fmin ? rmin[q] : fmin;
-        __syncthreads();
-        if (fmin <= dec) {
-            int bad = 0;
-            if (threadIdx.x == 0) bad = (ld_agent(error) != 0) || (++spins > spin_limit);
-            if (__syncthreads_or(bad)) {
-                if (threadIdx.x == 0) st_agent(error, (int)OPF_EHANG);
-                return;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        spins = 0;
-        // ---- decide iterations dec+1 .. fmin in order (at most kDecisionLag)
-        for (long long u = dec + 1; u <= fmin; ++u) {
-            const int slot = (int)(u % kDecisionLag);
-            double acc5[5] = {0, 0, 0, 0, 0};
-            for (int q0 = threadIdx.x; q0 < G; q0 += kBatch * NT) {
-                double pv[kBatch][5];
-#pragma unroll
-                for (int k = 0; k < kBatch; ++k) {
-                    const int q = q0 + k * NT;
-                    const double* pp = v.partials + ((size_t)slot * G + (q < G ? q : 0)) * 5;
-#pragma unroll
-                    for (int i = 0; i < 5; ++i) pv[k][i] = q < G ? ld_agent(&pp[i]) : 0.0;
+                    for (int h = 0; h < kRec; ++h) wd[k][h] = ld_agent(rec + (size_t)h * G + q);
+                    pending |= 1u << k;
                 }
-                // same summation order as a plain strided loop over q
+            }
+            for (;;) {
+                unsigned stale = 0;
 #pragma unroll
                 for (int k = 0; k < kBatch; ++k)
+                    if (((pending >> k) & 1u) && !tags_are<kRec>(wd[k], tag)) stale |= 1u << k;
+                if (!stale || bad) break;
+                __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-                    for (int i = 0; i < 5; ++i)
-                        if (q0 + k * NT < G) acc5[i] += pv[k][i];
+                for (int k = 0; k < kBatch; ++k)
+                    if ((stale >> k) & 1u)
+#pragma unroll
+                        for (int h = 0; h < kRec; ++h) wd[k][h] = ld_agent(rec + (size_t)h * G + q0 + k * NT);
+                pending = stale;
+                bad = wait_expired(++spins, error, spin_limit);
             }
 #pragma unroll
-            for (int i = 0; i < 5; ++i) acc5[i] = wave_sum_p(acc5[i]);
-            if (lane == 0)
+            for (int k = 0; k < kBatch; ++k)
+                if (q0 + k * NT < G)
 #pragma unroll
-                for (int i = 0; i < 5; ++i) rred[wv][i] = acc5[i];
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double S[5] = {0, 0, 0, 0, 0};
-                for (int q = 0; q < NT / 64; ++q)
-#pragma unroll
-                    for (int i = 0; i < 5; ++i) S[i] += rred[q][i];
-                const double pres = sqrt(S[0]);
-                const double dres = v.rho_d * sqrt(S[1]);
-                const double ep = v.eps_rel * fmax(sqrt(S[2]), sqrt(S[3]));
-                const double ed = v.eps_rel * sqrt(S[4]);
-                if (u - 1 < v.hist_cap) {
-                    v.hist[(u - 1) * 4 + 0] = pres;
-                    v.hist[(u - 1) * 4 + 1] = dres;
-                    v.hist[(u - 1) * 4 + 2] = ep;
-                    v.hist[(u - 1) * 4 + 3] = ed;
-                }
-                int end = 1, finished = 1, status = OPF_OK;
-                if (!(isfinite(pres) && isfinite(dres) && isfinite(ep) && isfinite(ed))) {
-                    status = OPF_ENUMERIC;
-                } else if (v.check && pres <= ep && dres <= ed) {
-                    status = OPF_OK;
-                } else if (u >= v.max_iter) {
-                    status = v.check ? OPF_NOT_CONVERGED : OPF_OK;
-                } else if (u >= t0 + v.chunk) {
-                    finished = 0;                      // pause
-                } else {
-                    end = 0;
-                }
-                if (end) {
-                    ctrl->iter = u;
-                    ctrl->status = status;
-                    ctrl->res[0] = pres;
-                    ctrl->res[1] = dres;
-                    ctrl->res[2] = ep;
-                    ctrl->res[3] = ed;
-                    ctrl->stop = finished;
-                    st_agent(v.dec_stop, u);
-                    drain_memory();          // the end iteration is visible before dec_iter reaches it
-                    st_agent(v.dec_iter, u);
-                }
-                rstop = end;
-            }
-            __syncthreads();
-            if (rstop) return;
+                    for (int i = 0; i < 5; ++i) {
+                        const u64 two[2] = {wd[k][2 * i], wd[k][2 * i + 1]};
+                        acc5[i] += Tag<double>::unpack(two);
+                    }
         }
-        if (threadIdx.x == 0) st_agent(v.dec_iter, fmin);
-        dec = fmin;
+        if (__syncthreads_or(bad)) {
+            if (threadIdx.x == 0) st_agent(error, (int)OPF_EHANG);
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < 5; ++i) acc5[i] = wave_sum_p(acc5[i]);
+        if (lane == 0)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) rred[wv][i] = acc5[i];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double S[5] = {0, 0, 0, 0, 0};
+            for (int q = 0; q < NT / 64; ++q)
+#pragma unroll
+                for (int i = 0; i < 5; ++i) S[i] += rred[q][i];
+            const double pres = sqrt(S[0]);
+            const double dres = v.rho_d * sqrt(S[1]);
+            const double ep = v.eps_rel * fmax(sqrt(S[2]), sqrt(S[3]));
+            const double ed = v.eps_rel * sqrt(S[4]);
+            if (u - 1 < v.hist_cap) {
+                v.hist[(u - 1) * 4 + 0] = pres;
+                v.hist[(u - 1) * 4 + 1] = dres;
+                v.hist[(u - 1) * 4 + 2] = ep;
+                v.hist[(u - 1) * 4 + 3] = ed;
+            }
+            int end = 1, finished = 1, status = OPF_OK;
+            if (!(isfinite(pres) && isfinite(dres) && isfinite(ep) && isfinite(ed))) {
+                status = OPF_ENUMERIC;
+            } else if (v.check && pres <= ep && dres <= ed) {
+                status = OPF_OK;
+            } else if (u >= v.max_iter) {
+                status = v.check ? OPF_NOT_CONVERGED : OPF_OK;
+            } else if (u >= t0 + v.chunk) {
+                finished = 0;                      // pause
+            } else {
+                end = 0;
+            }
+            if (end) {
+                ctrl->iter = u;
+                ctrl->status = status;
+                ctrl->res[0] = pres;
+                ctrl->res[1] = dres;
+                ctrl->res[2] = ep;
+                ctrl->res[3] = ed;
+                ctrl->stop = finished;
+                st_agent(v.dec_stop, u);
+                drain_memory();          // the end iteration is visible before dec_iter reaches it
+            }
+            st_agent(v.dec_iter, u);
+            rstop = end;
+        }
+        __syncthreads();
+        if (rstop) return;
     }
 }
 
@@ -317,16 +311,17 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
         cost = a.cost[d];
     }
     const int2 wi = a.winfo[w];
-    const T* Fw = a.F + (size_t)wi.y * 64;
-    if (a.lds_factors) {
-        // static factors of this workgroup's wavefronts, copied once into LDS
-        extern __shared__ __align__(16) unsigned char dyn_lds[];
-        T* Fl = reinterpret_cast<T*>(dyn_lds);
+    const T* Fg = a.F + (size_t)wi.y * 64;
+    // static factors of this workgroup's wavefronts, copied once into LDS when
+    // they fit (kept as a separate pointer so the loads stay LDS loads)
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    T* Fl = reinterpret_cast<T*>(dyn_lds);
+    const bool in_lds = a.lds_factors != 0;
+    if (in_lds) {
         int off = 0;
         for (int q = 0; q < wv; ++q) off += a.winfo[b * WPB + q].x;
         Fl += (size_t)off * 64;
-        for (int k = 0; k < wi.x; ++k) Fl[k * 64 + lane] = Fw[k * 64 + lane];
-        Fw = Fl;
+        for (int k = 0; k < wi.x; ++k) Fl[k * 64 + lane] = Fg[k * 64 + lane];
     }
     const int base = meta & 255;
     const bool owner = (meta >> 16) & 1;
@@ -358,26 +353,31 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
         T acc = 0;
         if (live) {
             u64 wd[kCopyRegs][W];
+            unsigned pending = 0;       // copies whose word of iteration t has not arrived
 #pragma unroll
             for (int k = 0; k < kCopyRegs; ++k) {
-                if (k < cn && cp[k] != d) load_words<W>(pubr + (size_t)cp[k] * W, wd[k]);
+                if (k < cn && cp[k] != d) {
+                    load_words<W>(pubr + (size_t)cp[k] * W, wd[k]);
+                    pending |= 1u << k;
+                }
+            }
+            // re-load every stale copy at once, so one round trip covers them all
+            for (;;) {
+                unsigned stale = 0;
+#pragma unroll
+                for (int k = 0; k < kCopyRegs; ++k)
+                    if (((pending >> k) & 1u) && !tags_are<W>(wd[k], tag)) stale |= 1u << k;
+                if (!stale || bad) break;
+                __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                for (int k = 0; k < kCopyRegs; ++k)
+                    if ((stale >> k) & 1u) load_words<W>(pubr + (size_t)cp[k] * W, wd[k]);
+                pending = stale;
+                bad = wait_expired(++spins, error, spin_limit);
             }
 #pragma unroll
             for (int k = 0; k < kCopyRegs; ++k) {
-                if (k < cn) {
-                    T v;
-                    if (cp[k] == d) {
-                        v = copy_term(zh[0], lh[0], inv_rho);
-                    } else {
-                        while (!tags_are<W>(wd[k], tag) && !bad) {
-                            __builtin_amdgcn_s_sleep(1);
-                            load_words<W>(pubr + (size_t)cp[k] * W, wd[k]);
-                            bad = wait_expired(++spins, error, spin_limit);
-                        }
-                        v = Tag<T>::unpack(wd[k]);
-                    }
-                    acc += v;
-                }
+                if (k < cn) acc += (cp[k] == d) ? copy_term(zh[0], lh[0], inv_rho) : Tag<T>::unpack(wd[k]);
             }
             for (int k = kCopyRegs; k < cn; ++k) {
                 const int e = a.clist[cs + k];
@@ -392,10 +392,6 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
             }
         }
         if (threadIdx.x == 0) {
-            // the gathers above waited for this thread's earlier stores too:
-            // the residual partials of iteration t are complete
-            drain_memory();
-            if (t > t0) st_agent(&a.flags[b], t);
             while (dseen < tn - LAG && !bad && !errseen) {
                 __builtin_amdgcn_s_sleep(1);
                 dseen = ld_agent(a.dec_iter);
@@ -424,15 +420,18 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
             }
             break;
         }
-        // ---- global update, local projection, dual update, residual terms
+        // ---- global update, local projection, dual update, residual terms.
+        // The projection input is exchanged through this wavefront's own LDS
+        // row only, and a wavefront's LDS operations complete in order, so a
+        // wavefront barrier suffices here.
         T xg = 0;
         if (live) xg = consensus_value(acc, cost, inv_rho, cn, lo, hi);
         vsh[wv][lane] = live ? projection_input(xg, lh[0], inv_rho) : (T)0;
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
         double s[5] = {0, 0, 0, 0, 0};
         if (live) {
-            T z = bb;
-            for (int k = 0; k < wi.x; ++k) z = fmadd(Fw[k * 64 + lane], vsh[wv][(base + k) & 63], z);
+            const T z = in_lds ? project_row(Fl, vsh[wv], base, lane, wi.x, bb)
+                               : project_row(Fg, vsh[wv], base, lane, wi.x, bb);
             const T ln = dual_step(lh[0], rho, xg, z);
             u64 wout[W];
             Tag<T>::pack(copy_term(z, ln, inv_rho), (unsigned)tn, wout);
@@ -455,21 +454,23 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
             lh[0] = ln;
             xh[0] = xg;
         }
-        // ---- workgroup residual partial of iteration tn (flagged one iteration later)
+        // ---- workgroup residual record of iteration tn: sum i over the
+        // wavefronts in order (thread i), two tagged words per sum
 #pragma unroll
         for (int i = 0; i < 5; ++i) s[i] = wave_sum_p(s[i]);
         if (lane == 0)
 #pragma unroll
             for (int i = 0; i < 5; ++i) red[wv][i] = s[i];
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double bsum[5] = {0, 0, 0, 0, 0};
-            for (int q = 0; q < WPB; ++q)
-#pragma unroll
-                for (int i = 0; i < 5; ++i) bsum[i] += red[q][i];
-            double* pp = a.partials + ((size_t)(tn % LAG) * G + b) * 5;
-#pragma unroll
-            for (int i = 0; i < 5; ++i) st_agent(&pp[i], bsum[i]);
+        if (threadIdx.x < 5) {
+            const int i = threadIdx.x;
+            double bsum = 0.0;
+            for (int q = 0; q < WPB; ++q) bsum += red[q][i];
+            u64 two[2];
+            Tag<double>::pack(bsum, (unsigned)tn, two);
+            u64* rw = a.records + ((size_t)(tn % LAG) * kRec + 2 * i) * G + b;
+            st_agent(rw, two[0]);
+            st_agent(rw + G, two[1]);
         }
         t = tn;
     }
@@ -481,7 +482,7 @@ __device__ __forceinline__ InstanceView<T> view_of(const IterArgs<T>& a, const P
     v.F = a.F; v.winfo = a.winfo; v.var = a.var; v.meta = a.meta; v.cstart = a.cstart; v.ccnt = a.ccnt;
     v.clist = a.clist; v.bbar = a.bbar; v.lo = a.lo; v.hi = a.hi; v.cost = a.cost;
     v.z0 = a.z0; v.z1 = a.z1; v.l0 = a.l0; v.l1 = a.l1; v.x0 = a.x0; v.x1 = a.x1;
-    v.pub = p.pub; v.flags = p.flags; v.partials = p.partials; v.dec_iter = p.dec_iter; v.dec_stop = p.dec_stop;
+    v.pub = p.pub; v.records = p.records; v.dec_iter = p.dec_iter; v.dec_stop = p.dec_stop;
     v.ctrl = a.ctrl; v.hist = a.hist; v.hist_cap = a.hist_cap; v.waves = a.waves; v.check = p.check;
     v.lds_factors = p.lds_factors; v.rho = a.rho; v.inv_rho = a.inv_rho; v.rho_d = a.rho_d;
     v.eps_rel = a.eps_rel; v.max_iter = p.max_iter; v.chunk = 0x3fffffffffffffffll;
@@ -505,7 +506,7 @@ __device__ __forceinline__ InstanceView<double> view_of(const InstDesc& D, const
     v.F = D.F; v.winfo = D.winfo; v.var = D.var; v.meta = D.meta; v.cstart = D.cstart; v.ccnt = D.ccnt;
     v.clist = D.clist; v.bbar = D.bbar; v.lo = D.lo; v.hi = D.hi; v.cost = D.cost;
     v.z0 = D.z0; v.z1 = D.z1; v.l0 = D.l0; v.l1 = D.l1; v.x0 = D.x0; v.x1 = D.x1;
-    v.pub = D.pub; v.flags = D.flags; v.partials = D.partials; v.dec_iter = D.dec; v.dec_stop = D.dec + 1;
+    v.pub = D.pub; v.records = D.records; v.dec_iter = D.dec; v.dec_stop = D.dec + 1;
     v.ctrl = D.ctrl; v.hist = nullptr; v.hist_cap = 0; v.waves = D.lanes / 64; v.check = D.ctrl->check;
     v.lds_factors = D.lds_factors; v.rho = D.rho; v.inv_rho = 1.0 / D.rho; v.rho_d = D.rho;
     v.eps_rel = D.eps_rel; v.max_iter = D.ctrl->max_iter; v.chunk = s.chunk;
@@ -525,7 +526,7 @@ __global__ __launch_bounds__(kServeWPB * 64) void admm_serve_kernel(const InstDe
 }
 
 // Before a serving launch: each work item prepares its own part of its solve
-// (published terms of the start iteration, flags; the reducer item resets the
+// (published terms of the start iteration, residual records; the reducer item resets the
 // decisions); the first item clears the launch's error flag.
 __global__ void serve_prepare_kernel(const InstDesc* descs, const int2* work) {
     const int2 wk = work[blockIdx.x];
@@ -542,7 +543,9 @@ __global__ void serve_prepare_kernel(const InstDesc* descs, const int2* work) {
             D.pub[d * 2 + h] = w[h];
             D.pub[(LP + d) * 2 + h] = w[h];
         }
-        if (threadIdx.x == 0) D.flags[wk.y] = t0;
+        // residual records of this workgroup: tag t0 matches no iteration of the launch
+        for (int q = threadIdx.x; q < kDecisionLag * kRec; q += blockDim.x)
+            D.records[(size_t)q * D.blocks + wk.y] = (u64)(unsigned)t0 << 32;
     } else if (threadIdx.x == 0) {
         D.dec[0] = t0;
         D.dec[1] = -1;
@@ -575,7 +578,8 @@ int serve_capacity(size_t lds_bytes) {
 
 // Before a launch: the published terms of the start iteration t0 (both parity
 // buffers, tag t0; the other buffer's tag t0 never matches a later
-// iteration), reducer flags and decisions at t0, error cleared.
+// iteration), residual records tagged t0 (stale), decisions at t0, error
+// cleared.
 template <typename T>
 __global__ void persistent_prepare_kernel(IterArgs<T> a, PersistArgs p, int G) {
     constexpr int W = Tag<T>::W;
@@ -593,7 +597,7 @@ __global__ void persistent_prepare_kernel(IterArgs<T> a, PersistArgs p, int G) {
             p.pub[(LP + i) * W + h] = w[h];
         }
     }
-    if (i < G) p.flags[i] = t0;
+    if ((size_t)i < (size_t)kDecisionLag * G * kRec) p.records[i] = (u64)(unsigned)t0 << 32;
     if (i == 0) {
         *p.dec_iter = t0;
         *p.dec_stop = -1;
@@ -605,7 +609,7 @@ template <typename T>
 hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G, hipStream_t st) {
     const size_t lds = p.lds_factors ? (size_t)p.lds_factor_cols * 64 * sizeof(T) : 0;
     const size_t LP = (size_t)a.waves * 64;
-    const int n = (int)std::max<size_t>(LP, (size_t)G);
+    const int n = (int)std::max<size_t>(LP, (size_t)kDecisionLag * G * kRec);
     hipLaunchKernelGGL((persistent_prepare_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, a, p, G);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

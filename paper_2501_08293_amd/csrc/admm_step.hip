@@ -152,9 +152,7 @@ __global__ __launch_bounds__(WPB * 64) void admm_step_kernel(IterArgs<T> a) {
         const int2 wi = a.winfo[w];
         const T* Fw = a.F + (size_t)wi.y * 64;
         const int base = meta & 255;
-        T acc = a.bbar[d];
-        for (int k = 0; k < wi.x; ++k) acc = fmadd(Fw[k * 64 + lane], vsh[wv][(base + k) & 63], acc);
-        const T zn = acc;
+        const T zn = project_row(Fw, vsh[wv], base, lane, wi.x, a.bbar[d]);
         const T ln = dual_step(lold, a.rho, xg, zn);
         zq[d] = zn;
         lq[d] = ln;

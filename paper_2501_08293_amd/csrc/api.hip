@@ -107,12 +107,15 @@ struct opf_admm_handle {
     int kernel = OPF_KERNEL_STEP;
     int capacity = 0;
     unsigned long long* pub = nullptr;   // published copy terms [2][LP][2] (tagged words)
-    long long* flags = nullptr;
+    unsigned long long* records = nullptr;   // persistent residual records [lag][blocks][10]
     long long* dec_iter = nullptr;
     long long* dec_stop = nullptr;
     int* dev_error = nullptr;
     int xcd_remap = 1;
     int* error_host = nullptr;     // pinned
+    double* devF = nullptr;        // factors from the device set-up (FP64, packed), else null
+    double* devBbar = nullptr;
+    int64_t devF_count = 0;
     int lds_cols = 0;              // factor columns of the largest workgroup
     int lds32 = 0, lds64 = 0;      // factors resident in LDS for each precision
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -164,8 +167,21 @@ template <typename T>
 int make_prec(opf_admm_handle* h, PrecState<T>& s) {
     const HostLayout& L = h->lay;
     int rc;
-    if ((rc = upload(h, &s.F, L.F))) return rc;
-    if ((rc = upload(h, &s.bbar, L.bbar))) return rc;
+    if (h->devF) {
+        // factors computed by the device set-up (FP64); narrowed for FP32
+        if (sizeof(T) == 8) {
+            s.F = reinterpret_cast<T*>(h->devF);
+            s.bbar = reinterpret_cast<T*>(h->devBbar);
+        } else {
+            if ((rc = dalloc(h, &s.F, (size_t)h->devF_count))) return rc;
+            if ((rc = dalloc(h, &s.bbar, (size_t)h->LP))) return rc;
+            HIPCHK(launch_narrow(h->devF, reinterpret_cast<float*>(s.F), h->devF_count, h->stream));
+            HIPCHK(launch_narrow(h->devBbar, reinterpret_cast<float*>(s.bbar), h->LP, h->stream));
+        }
+    } else {
+        if ((rc = upload(h, &s.F, L.F))) return rc;
+        if ((rc = upload(h, &s.bbar, L.bbar))) return rc;
+    }
     if ((rc = upload(h, &s.lo, L.lo))) return rc;
     if ((rc = upload(h, &s.hi, L.hi))) return rc;
     if ((rc = upload(h, &s.cost, L.cost))) return rc;
@@ -268,8 +284,7 @@ int run_phase_persistent(opf_admm_handle* h, PrecState<T>& s, long long max_iter
     IterArgs<T> a = iter_args(h, s);
     PersistArgs p;
     p.pub = h->pub;
-    p.flags = h->flags;
-    p.partials = h->partials;
+    p.records = h->records;
     p.dec_iter = h->dec_iter;
     p.dec_stop = h->dec_stop;
     p.error = h->dev_error;
@@ -420,6 +435,49 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
 
 }  // namespace
 
+// Device set-up: row reduction and factors of every component on the GPU,
+// written into the packed layout (FP64); any component found infeasible fails
+// the set-up as on the host.
+int device_factors(opf_admm_handle* h, const opf_problem* p) {
+    const HostLayout& L = h->lay;
+    const int S = L.S;
+    size_t lds = 0;
+    int64_t na = 0, nb = 0;
+    for (int q = 0; q < S; ++q) {
+        lds = std::max(lds, factor_lds_bytes(p->comp_m[q], p->comp_n[q]));
+        na += (int64_t)p->comp_m[q] * p->comp_n[q];
+        nb += p->comp_m[q];
+    }
+    if (lds > 64 * 1024)
+        return set_err(h, OPF_EINVAL, "device set-up: a component needs more than 64 KiB of LDS; use the host set-up");
+    const int W = L.waves;
+    h->devF_count = W ? L.wave_foff[W - 1] + (int64_t)L.wave_maxn[W - 1] * kWave : 0;
+    int rc;
+    double *dA = nullptr, *db = nullptr;
+    int64_t *daoff = nullptr, *dboff = nullptr, *dfoff = nullptr;
+    int *dm = nullptr, *dn = nullptr, *ddev = nullptr, *dstatus = nullptr;
+    if ((rc = dalloc(h, &h->devF, (size_t)std::max<int64_t>(h->devF_count, 1)))) return rc;
+    if ((rc = dalloc(h, &h->devBbar, (size_t)h->LP))) return rc;
+    HIPCHK(hipMemsetAsync(h->devF, 0, sizeof(double) * std::max<int64_t>(h->devF_count, 1), h->stream));
+    HIPCHK(hipMemsetAsync(h->devBbar, 0, sizeof(double) * h->LP, h->stream));
+    std::vector<double> A(p->A_vals, p->A_vals + na), b(p->b_vals, p->b_vals + nb);
+    std::vector<int32_t> m(p->comp_m, p->comp_m + S), n(p->comp_n, p->comp_n + S);
+    if ((rc = upload(h, &dA, A)) || (rc = upload(h, &db, b)) || (rc = upload(h, &daoff, L.comp_aoff)) ||
+        (rc = upload(h, &dboff, L.comp_boff)) || (rc = upload(h, &dfoff, L.wave_foff)) || (rc = upload(h, &dm, m)) ||
+        (rc = upload(h, &dn, n)) || (rc = upload(h, &ddev, L.comp_dev)) || (rc = dalloc(h, &dstatus, (size_t)S)))
+        return rc;
+    FactorJob job{dA, db, daoff, dboff, dm, dn, ddev, dfoff, h->devF, h->devBbar, dstatus, S};
+    HIPCHK(launch_factors(job, lds, h->stream));
+    std::vector<int> status(S, 0);
+    HIPCHK(hipMemcpyAsync(status.data(), dstatus, sizeof(int) * S, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int q = 0; q < S; ++q)
+        if (status[q] != 0)
+            return set_err(h, status[q], "row reduction found 0 = nonzero (inconsistent equations) in component " +
+                                             std::to_string(q));
+    return 0;
+}
+
 extern "C" {
 
 void opf_admm_default_options(opf_admm_options* o) {
@@ -503,6 +561,7 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     const int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     h->lay.block_waves = (opt.block_waves == 1 || opt.block_waves == 2 || opt.block_waves == 4 ||
                           opt.block_waves == 8) ? opt.block_waves : 4;
+    h->lay.factors_on_device = opt.setup_on_device == 1;
     int rc = build_layout(v, h->lay, err, threads);
     if (rc) {
         delete h;
@@ -510,7 +569,7 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     }
     h->LP = h->lay.waves * kWave;
     h->user_stream = (hipStream_t)hip_stream;
-    h->xcd_remap = opt.workgroup_order == 1 ? 0 : 1;
+    h->xcd_remap = opt.workgroup_order == 1 ? 1 : 0;
     h->wpb = h->lay.block_waves;
     auto fail = [&](int code) {
         std::string m = h->err;
@@ -541,6 +600,7 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     if ((rc = upload(h, &h->user_to_dev, L.user_to_dev))) return fail(rc);
     if ((rc = upload(h, &h->z0, L.z0))) return fail(rc);
     if ((rc = upload(h, &h->c, L.c_full))) return fail(rc);
+    if (L.factors_on_device && (rc = device_factors(h, p))) return fail(rc);
     if ((rc = dalloc(h, &h->warm_z, h->LP))) return fail(rc);
     if ((rc = dalloc(h, &h->warm_l, h->LP))) return fail(rc);
     if ((rc = dalloc(h, &h->user_z, L.L))) return fail(rc);
@@ -548,11 +608,10 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     if ((rc = dalloc(h, &h->xo, L.n))) return fail(rc);
     const int blocks = L.blocks;
     h->grid_blocks = blocks;
-    // residual partials: one slot per workgroup for the step kernel, a ring of
-    // kDecisionLag slots per workgroup for the persistent kernel
-    if ((rc = dalloc(h, &h->partials, (size_t)blocks * 5 * kDecisionLag + 10))) return fail(rc);
+    // residual partials of the step kernel; tagged records of the persistent kernel
+    if ((rc = dalloc(h, &h->partials, (size_t)blocks * 5 + 10))) return fail(rc);
     if ((rc = dalloc(h, &h->pub, (size_t)h->LP * 4))) return fail(rc);
-    if ((rc = dalloc(h, &h->flags, blocks))) return fail(rc);
+    if ((rc = dalloc(h, &h->records, (size_t)blocks * 10 * kDecisionLag))) return fail(rc);
     if ((rc = dalloc(h, &h->dec_iter, 1))) return fail(rc);
     if ((rc = dalloc(h, &h->dec_stop, 1))) return fail(rc);
     if ((rc = dalloc(h, &h->dev_error, 1))) return fail(rc);

@@ -41,7 +41,7 @@ size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Offsets of the arrays of one resident solve inside its arena region.
 struct Image {
     size_t winfo, var, meta, cstart, ccnt, clist, user_slot, F, bbar, lo, hi, cost, zdef, zdef_user;
-    size_t z0, z1, l0, l1, x0, x1, partials, pub, flags, dec, zu, lu, xo, plan, total;
+    size_t z0, z1, l0, l1, x0, x1, records, pub, dec, zu, lu, xo, plan, total;
 };
 
 struct Request {
@@ -143,9 +143,8 @@ Image plan_image(const HostLayout& L) {
     im.l1 = take(8 * LP);
     im.x0 = take(8 * (size_t)L.n);
     im.x1 = take(8 * (size_t)L.n);
-    im.partials = take(8 * 5 * (size_t)L.blocks * kDecisionLag);
+    im.records = take(8 * 10 * (size_t)L.blocks * kDecisionLag);
     im.pub = take(8 * 2 * 2 * LP);
-    im.flags = take(8 * (size_t)L.blocks);
     im.dec = take(16);
     im.zu = take(8 * (size_t)L.L);
     im.lu = take(8 * (size_t)L.L);
@@ -369,9 +368,8 @@ int admit_one(opf_server* s, std::unique_ptr<Request>& r, int slot_id) {
     D.l1 = reinterpret_cast<double*>(base + im.l1);
     D.x0 = reinterpret_cast<double*>(base + im.x0);
     D.x1 = reinterpret_cast<double*>(base + im.x1);
-    D.partials = reinterpret_cast<double*>(base + im.partials);
+    D.records = reinterpret_cast<unsigned long long*>(base + im.records);
     D.pub = reinterpret_cast<unsigned long long*>(base + im.pub);
-    D.flags = reinterpret_cast<long long*>(base + im.flags);
     D.dec = reinterpret_cast<long long*>(base + im.dec);
     D.lds_factors = q.lds_ok;
     D.ctrl = s->d_ctrls + slot_id;
@@ -510,7 +508,7 @@ void worker_loop(opf_server* s) {
     sa.error = s->d_error;
     sa.spin_limit = s->opt.admm.spin_limit > 0 ? s->opt.admm.spin_limit : 4000000LL;
     sa.chunk = std::max(1, s->opt.iters_per_poll);
-    sa.xcd_remap = s->opt.admm.workgroup_order == 1 ? 0 : 1;
+    sa.xcd_remap = s->opt.admm.workgroup_order == 1 ? 1 : 0;
     sa.lds_cols = kServeLdsCols;
     for (;;) {
         if (s->quit.load()) return;

@@ -36,6 +36,7 @@ struct HostLayout {
     int32_t max_nbrs = 0;       // largest neighbour list
     int32_t max_ns = 0, max_copies = 0;
     int64_t sum_ns2 = 0;
+    bool factors_on_device = false;   // input: leave F and bbar empty (computed by the device set-up)
 
     // per wavefront
     std::vector<int32_t> wave_maxn;   // columns stored for the wavefront
@@ -62,6 +63,11 @@ struct HostLayout {
     std::vector<int32_t> nbr_list;
 
     std::vector<double> c_full;       // [n] objective (for c^T x)
+
+    // per component (filled when factors_on_device): first device slot
+    // (wave * 64 + base lane), offsets of its A block and b entries
+    std::vector<int32_t> comp_dev;
+    std::vector<int64_t> comp_aoff, comp_boff;
 };
 
 // Returns 0 or an OPF_E* code with a message in err.

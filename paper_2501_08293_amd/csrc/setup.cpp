@@ -192,11 +192,12 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
     for (int i = 0; i < n; ++i)
         if (cnt[i] == 0) { err = fmt("global variable has no local copy:", i); return OPF_EUNCOVERED; }
 
-    // ---- factors, in parallel over components
+    // ---- factors, in parallel over components (unless the device computes them)
+    const bool host_factors = !out.factors_on_device;
     std::vector<int64_t> foff(S + 1);
     foff[0] = 0;
-    for (int s = 0; s < S; ++s) foff[s + 1] = foff[s] + (int64_t)p.comp_n[s] * p.comp_n[s];
-    std::vector<double> Fs(foff[S]), bb(L);
+    for (int s = 0; s < S; ++s) foff[s + 1] = host_factors ? foff[s] + (int64_t)p.comp_n[s] * p.comp_n[s] : 0;
+    std::vector<double> Fs(foff[S]), bb(host_factors ? L : 0);
     std::atomic<int> next(0), bad(-1), badcode(0);
     auto work = [&]() {
         for (;;) {
@@ -211,10 +212,12 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
         }
     };
     threads = std::max(1, std::min(threads, 64));
-    std::vector<std::thread> pool;
-    for (int t = 1; t < threads; ++t) pool.emplace_back(work);
-    work();
-    for (auto& th : pool) th.join();
+    if (host_factors) {
+        std::vector<std::thread> pool;
+        for (int t = 1; t < threads; ++t) pool.emplace_back(work);
+        work();
+        for (auto& th : pool) th.join();
+    }
     if (bad.load() >= 0) {
         err = fmt("row reduction found 0 = nonzero (inconsistent equations) in component", bad.load());
         return badcode.load();
@@ -335,7 +338,12 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
         out.wave_foff[wi] = ftotal;
         ftotal += (int64_t)maxn * kWave;
     }
-    out.F.assign(ftotal, 0.0);
+    out.F.assign(host_factors ? ftotal : 0, 0.0);
+    if (!host_factors) {
+        out.comp_dev.assign(S, -1);
+        out.comp_aoff.assign(aoff.begin(), aoff.end() - 1);
+        out.comp_boff.assign(boff.begin(), boff.end() - 1);
+    }
     out.max_ns = 0;
     out.sum_ns2 = 0;
     for (int wi = 0; wi < W; ++wi) {
@@ -345,6 +353,7 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
             const int k = p.comp_n[s];
             out.max_ns = std::max(out.max_ns, k);
             out.sum_ns2 += (int64_t)k * k;
+            if (!host_factors) out.comp_dev[s] = wi * kWave + lane;
             for (int j = 0; j < k; ++j) {
                 const int d = wi * kWave + lane + j;
                 const int us = (int)(ioff[s] + j);
@@ -352,6 +361,7 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
                 out.meta[d] = lane | (k << 8);
                 out.user_slot[d] = us;
                 out.user_to_dev[us] = d;
+                if (!host_factors) continue;
                 out.bbar[d] = bb[us];
                 for (int q = 0; q < k; ++q)
                     out.F[fb + (int64_t)q * kWave + lane + j] = Fs[foff[s] + (int64_t)j * k + q];
