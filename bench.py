@@ -115,13 +115,16 @@ def copy_calibration():
 
 
 def traffic_from_profiles(workload, precision):
-    """HBM bytes per iteration from committed counter runs, if they were
-    taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_admm_persistent_{workload}_{precision}.json")
+    """HBM bytes per iteration from the committed counter summary (the json
+    block of profiles/traffic_admm_persistent_<workload>_<precision>.md), if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_admm_persistent_{workload}_{precision}.md")
     if not os.path.exists(path):
         return None
     try:
-        d = json.load(open(path))
+        text = open(path).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        d = json.loads(block)
     except Exception:
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
