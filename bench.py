@@ -159,6 +159,11 @@ def single_instance(args, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     solver.close()
+    # the same set-up with the component factors computed on the device
+    dev_setup = Solver(*flat, rho=100.0, eps_rel=args.eps, precision=prec, kernel=kern,
+                       block_waves=args.block_waves, setup_on_device=True, stream=stream.cuda_stream)
+    setup_ms_device = dev_setup.info().setup_ms
+    dev_setup.close()
     iters = sum(r["iterations"] for r in results)
     it32 = sum(r["iterations_fp32"] for r in results)
     it64 = iters - it32
@@ -203,6 +208,7 @@ def single_instance(args, torch):
             "status": results[-1]["status"],
             "objective": results[-1]["objective"],
             "setup_ms": round(info.setup_ms, 1),
+            "setup_ms_device_factors": round(setup_ms_device, 1),
             "generator_s": round(gen_s, 2),
             "waves": info.waves,
             "lanes": info.lanes,
@@ -315,12 +321,14 @@ def serve_leg(args, torch):
     lat = np.array([done[i]["latency_ms"] for i in range(N)])
     ok = sum(1 for i in range(N) if done[i]["status"] == 0)
     warm = sum(1 for i in range(N) if done[i]["warm_components"] > 0)
+    print(f"[bench] served {N} requests in {span:.1f} s; one-at-a-time baseline next", file=sys.stderr, flush=True)
     # baseline: the same trace served one solve at a time, FIFO, cold start,
     # with the single-instance solver (set-up included, as in the runtime)
     base_lat = []
     base_ok = 0
     free_at = 0.0
     base_obj_err = []
+    base_obj = []
     t_b = time.perf_counter()
     for i in range(N):
         start = max(arrivals[i], free_at)
@@ -335,7 +343,18 @@ def serve_leg(args, torch):
         free_at = time.perf_counter() - t_b
         base_lat.append(1e3 * (free_at - arrivals[i]))
         base_obj_err.append(abs(r["objective"] - done[i]["objective"]) / max(1e-12, abs(r["objective"])))
+        base_obj.append(r["objective"])
     base_lat = np.array(base_lat)
+    # accuracy at equal termination test: a sample of the smaller requests
+    # solved to eps_rel = 1e-6 as the reference
+    samp = [i for i in range(N) if reqs[i][1].feeder.n_bus <= 1500][:6]
+    err_srv, err_base = [], []
+    for i in samp:
+        s = Solver(*reqs[i][3], rho=100.0, eps_rel=1e-6, check_every=256, stream=st.cuda_stream)
+        ref = s.solve()["objective"]
+        s.close()
+        err_srv.append(abs(done[i]["objective"] - ref) / max(1e-12, abs(ref)))
+        err_base.append(abs(base_obj[i] - ref) / max(1e-12, abs(ref)))
     return {
         "workload": f"{N} requests, Poisson {args.serve_rate:g}/s, {args.serve_families} feeder families "
                     f"(13-8500 buses log-uniform, tie-switch reconfigurations, fresh loads), eps_rel={args.serve_eps:g}",
@@ -349,6 +368,9 @@ def serve_leg(args, torch):
                                    "converged": base_ok},
         "speedup_solves_per_s": round((ok / span) / max(base_ok / free_at, 1e-9), 2),
         "max_objective_rel_diff_vs_baseline": float(max(base_obj_err)),
+        "objective_rel_err_vs_eps1e-6_sample": {"requests": len(samp),
+                                               "served_max": float(max(err_srv)) if samp else None,
+                                               "one_at_a_time_max": float(max(err_base)) if samp else None},
         "launches": int(sstats["launches"]), "generator_s": round(gen_s, 1),
     }
 
@@ -367,13 +389,21 @@ def main():
         leg = batch_leg(args, torch) if args.only == "batch" else serve_leg(args, torch)
         print(json.dumps({args.only: leg}), flush=True)
         return
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    progress("single instance")
     line, inst = single_instance(args, torch)
+    progress(f"single instance done: {line['ms_per_step']} ms per solve")
     if not args.skip_batch:
         line["batch"] = batch_leg(args, torch)
+        progress(f"batch done: {line['batch']['time_to_all_ms']} ms")
     if not args.skip_serve:
         line["serving"] = serve_leg(args, torch)
+        progress(f"serving done: {line['serving']['solves_per_s']} solves/s")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, args.eps, args.cpu_seconds)
+        progress("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 

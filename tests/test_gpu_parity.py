@@ -255,6 +255,54 @@ def test_full_size_8500bus_solve_matches_golden_fp64():
     s.close()
 
 
+def test_full_size_8500bus_mixed_benchmark_configuration():
+    """The configuration the benchmark times (mixed precision: FP32 persistent
+    bulk iterations, FP64 residual sums, FP64 polish) at the full 8500-bus
+    size: FP32 iterates after 20 iterations within 1e-5 relative of the FP64
+    oracle, and the solve at eps_rel = 1e-3 within the mixed-precision bar
+    (objective and voltages 1e-4 relative) of the oracle's solve."""
+    from paper_2501_08293_amd import OPF_PREC_MIXED
+    _say("[gpu] 8500bus mixed: t=20 FP32 iterates and solve to 1e-3 vs golden")
+    inst = _inst("8500bus")
+    P = _oracle("8500bus")
+    ref = admm.solve(P, rho=RHO, eps_rel=1e-4, fixed_iters=20)
+    s = _solver(inst, rho=RHO, eps_rel=1e-3, precision=OPF_PREC_MIXED, check_every=1024)
+    out = s.solve(fixed_iters=20)
+    assert out["iterations_fp32"] == 20
+    assert _rel(out["x"], ref.x) < 1e-5
+    assert _rel(out["z"], ref.z) < 1e-5
+    g = _golden("8500bus", 1e-3)
+    out = s.solve()
+    s.close()
+    assert out["status"] == 0 and out["iterations_fp32"] > 0
+    assert abs(out["objective"] - g["objective"]) <= 1e-4 * abs(g["objective"])
+    w = out["x"][g["w_index"]]
+    assert np.max(np.abs(w - np.array(g["w_value"])) / np.abs(np.array(g["w_value"]))) <= 1e-4
+    _say(f"  iterations {out['iterations']} ({out['iterations_fp32']} FP32), golden {g['iterations']}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_thirty_thousand_component_size_fixed_iterations(prec):
+    """The ~30k-component size (21000-bus feeder, S = 29393): too large for a
+    co-resident persistent grid, so the automatic choice is the step schedule;
+    iterates after 10 iterations match the oracle (FP64 bar 1e-9; FP32 bar
+    1e-5 on x and on the scaled dual lambda / rho, the quantity the updates
+    use: lambda itself carries rho times the FP32 rounding of x - z)."""
+    from paper_2501_08293_amd import OPF_PREC_FP64, OPF_PREC_MIXED
+    _say(f"[gpu] 21000bus fixed-iteration parity t=10 {prec}")
+    inst = _inst("21000bus")
+    P = _oracle("21000bus")
+    ref = admm.solve(P, rho=RHO, eps_rel=1e-4, fixed_iters=10, record=False)
+    s = _solver(inst, rho=RHO, eps_rel=1e-4, precision=OPF_PREC_FP64 if prec == "fp64" else OPF_PREC_MIXED)
+    info = s.info()
+    out = s.solve(fixed_iters=10)
+    s.close()
+    assert info.S == inst.S
+    tol = 1e-9 if prec == "fp64" else 1e-5
+    assert _rel(out["x"], ref.x) < tol
+    assert _rel(out["lam"] / RHO, ref.lam / RHO) < tol
+
+
 def test_autotuned_configuration_solves_correctly():
     """The autotuner picks a schedule and workgroup shape by timing short runs
     on the problem; the chosen configuration still matches the oracle."""
