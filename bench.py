@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-eps", type=float, default=1e-3)
+    ap.add_argument("--serve-chunk", type=int, default=256,
+                    help="iterations each resident solve runs per shared launch")
     ap.add_argument("--only", choices=["batch", "serve"], default=None,
                     help="run only this leg and print its record (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -259,6 +261,14 @@ def batch_leg(args, torch):
     mfma_flops = info.waves * chunks * 4 * 4 * 6 * (2 * 32 * 32 * 16) * T
     useful_flops = 2 * info.sum_ns2 * int(it.sum())
     tf = mfma_flops / wall / 1e12
+    # algorithmic bytes of one batch iteration (FP32 state, per scenario column):
+    # z and lambda read+write and bbar per slot (20 L), the consensus reads of
+    # z and lambda of every copy of each slot's variable (8 sum_i N_i^2), the x
+    # write (4 n); plus the three bf16 factor planes once (3 * 2 * 64 * 64 per wave)
+    cnt = np.bincount(np.concatenate([c.idx for c in inst.comps]), minlength=inst.n).astype(np.int64)
+    per_col = 20 * inst.L + 8 * int((cnt * cnt).sum()) + 4 * inst.n
+    bytes_iter = 64 * chunks * per_col + 3 * 2 * 64 * 64 * info.waves
+    gbs = bytes_iter * T / wall / 1e9
     return {
         "workload": f"{inst.name}: {K} load scenarios (lognormal(0, 0.3) per bus), shared A_s; eps_rel={args.eps:g}",
         "scenarios": K, "converged": int(out["converged"]), "status": int(out["status"]),
@@ -267,6 +277,8 @@ def batch_leg(args, torch):
         "scenario_solves_per_s": round(K / wall, 2),
         "scenario_iterations_per_s": round(float(it.sum()) / wall, 1),
         "us_per_batch_iteration": round(1e6 * wall / max(T, 1), 2),
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_iteration": int(bytes_iter)},
         "mfma": {"issued_tflops": round(tf, 2), "peak_tflops_bf16_dense": BF16_DENSE_PEAK_TFLOPS,
                  "frac": round(tf / BF16_DENSE_PEAK_TFLOPS, 5),
                  "useful_fraction_of_issued": round(useful_flops * 6 / max(mfma_flops, 1), 4)},
@@ -301,7 +313,7 @@ def serve_leg(args, torch):
         reqs.append((fid, inst, keys, (inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, cm, cn, A, b, idx)))
     # continuous batching through the serving runtime
     st = torch.cuda.Stream()
-    srv = Server(rho=100.0, eps_rel=args.serve_eps, iters_per_poll=32, arena_bytes=8 << 30,
+    srv = Server(rho=100.0, eps_rel=args.serve_eps, iters_per_poll=args.serve_chunk, arena_bytes=8 << 30,
                  max_workgroups=16384, setup_threads=6, stream=st.cuda_stream)
     done = {}
     ids = {}
