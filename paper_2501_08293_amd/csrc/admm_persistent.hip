@@ -52,11 +52,6 @@ __device__ __forceinline__ void drain_memory() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-__device__ __forceinline__ double wave_sum_p(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 __device__ __forceinline__ long long wave_min_p(long long v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -220,7 +215,7 @@ __device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int*
             return;
         }
 #pragma unroll
-        for (int i = 0; i < 5; ++i) acc5[i] = wave_sum_p(acc5[i]);
+        for (int i = 0; i < 5; ++i) acc5[i] = wave_total(acc5[i]);
         if (lane == 0)
 #pragma unroll
             for (int i = 0; i < 5; ++i) rred[wv][i] = acc5[i];
@@ -457,7 +452,7 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
         // ---- workgroup residual record of iteration tn: sum i over the
         // wavefronts in order (thread i), two tagged words per sum
 #pragma unroll
-        for (int i = 0; i < 5; ++i) s[i] = wave_sum_p(s[i]);
+        for (int i = 0; i < 5; ++i) s[i] = wave_total(s[i]);
         if (lane == 0)
 #pragma unroll
             for (int i = 0; i < 5; ++i) red[wv][i] = s[i];

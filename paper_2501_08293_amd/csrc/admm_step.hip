@@ -35,7 +35,7 @@ __device__ __forceinline__ void finish_iteration(const double (&s)[5], double* p
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double r[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) r[i] = wave_sum(s[i]);
+    for (int i = 0; i < 5; ++i) r[i] = wave_total(s[i]);
     if (lane == 0) {
 #pragma unroll
         for (int i = 0; i < 5; ++i) red[wv][i] = r[i];
@@ -67,7 +67,7 @@ __device__ __forceinline__ void finish_iteration(const double (&s)[5], double* p
             a[i] += __hip_atomic_load(&partials[(size_t)bidx * 5 + i], __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) a[i] = wave_sum(a[i]);
+    for (int i = 0; i < 5; ++i) a[i] = wave_total(a[i]);
     __syncthreads();
     if (lane == 0)
 #pragma unroll
