@@ -285,3 +285,35 @@ def test_termination_test_literal_reading():
     ok = (h[:, 0] <= h[:, 2]) & (h[:, 1] <= h[:, 3])
     assert ok[-1] and not ok[:-1].any()
     assert r.iterations == len(h)
+
+
+# --------------------------------------------------------------------------
+# the same invariants on the edge-case shapes of the random LP (64-slot and
+# equation-free components, a repeated row, a ten-copy variable, infinite bounds)
+# --------------------------------------------------------------------------
+
+def test_invariants_hold_on_edge_case_shapes():
+    from opfgen.random_lp import random_instance
+    P = admm.setup(random_instance(0))
+    for A, b, Ab, bb in zip(P.A, P.b, P.Abar, P.bbar):
+        n = A.shape[1]
+        if A.shape[0] == 0:                 # no equations: the projection is the identity
+            np.testing.assert_allclose(-Ab, np.eye(n), atol=0)
+            assert np.all(bb == 0)
+            continue
+        pinv = np.linalg.pinv(A)
+        np.testing.assert_allclose(-Ab, np.eye(n) - pinv @ A, atol=1e-10)
+        np.testing.assert_allclose(bb, pinv @ b, atol=1e-10)
+    traj = _trajectory(P, 40)
+    for x, z, _, lam in traj:
+        assert np.all(x >= P.lb) and np.all(x <= P.ub)
+        for s, (A, b) in enumerate(zip(P.A, P.b)):
+            o = P.offs[s]
+            k = A.shape[1]
+            if A.shape[0]:
+                assert np.max(np.abs(A @ z[o:o + k] - b)) <= 1e-10 * max(1.0, np.max(np.abs(b)))
+            F = -P.Abar[s]
+            assert np.max(np.abs(F @ lam[o:o + k])) <= 1e-9 * max(1.0, np.max(np.abs(lam[o:o + k])))
+    r = admm.solve(P, rho=RHO, eps_rel=1e-6, fixed_iters=400)
+    m = r.history[:, 0] ** 2 + (r.history[:, 1] / RHO) ** 2
+    assert np.all(np.diff(m[1:]) <= 1e-10 * m[1:-1])
