@@ -258,6 +258,23 @@ typedef struct opf_batch_result {
 int opf_admm_setup_batch(const opf_problem* p, const double* b_scen, int32_t K, const opf_admm_options* o,
                          void* hip_stream, opf_admm_batch** out);
 
+/*
+ * As opf_admm_setup_batch, for load models whose equations change with the
+ * scenario (voltage-dependent ZIP loads: the coefficient of the bus voltage in
+ * VDLM-1/2 scales with the load).  `a_pos` [nv] are positions in p->A_vals
+ * (int64, each inside one component's block) whose value differs per scenario;
+ * `a_scen` [K][nv] (row-major) holds those values for every scenario.
+ * Components that contain such a position are factored once per scenario
+ * (Section IV-B row reduction, closed_2) and packed into wavefronts of their
+ * own, whose local update runs as a per-scenario FP32 product; all other
+ * components keep the shared split-bf16 MFMA product.  nv = 0 is
+ * opf_admm_setup_batch.  Errors as opf_admm_setup_batch; a scenario whose
+ * patched equations are contradictory gives OPF_EINFEASIBLE_COMPONENT.
+ */
+int opf_admm_setup_batch_ex(const opf_problem* p, const double* b_scen, int32_t K, int64_t nv,
+                            const int64_t* a_pos, const double* a_scen, const opf_admm_options* o,
+                            void* hip_stream, opf_admm_batch** out);
+
 /* Runs Algorithm 1 for all scenarios from the default start point until every
    scenario has met its test or max_iter.  Returns OPF_OK when all converged,
    OPF_NOT_CONVERGED if some reached max_iter, OPF_ENUMERIC, or an error. */

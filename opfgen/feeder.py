@@ -359,9 +359,12 @@ def make_13bus(seed: int = 0, zip_variant: bool = False) -> Feeder:
 
 def make_radial(n_bus: int, seed: int, *, n_loads: int, load_mu_kw: float, load_sigma: float,
                 n_der: int, trunk_frac: float, p_single: float, v_ll_kv: float,
-                name: str, der_cap=(50.0, 200.0), tag: int = 0, tree: str = "dfs") -> Feeder:
+                name: str, der_cap=(50.0, 200.0), tag: int = 0, tree: str = "dfs",
+                zip_mix: bool = False) -> Feeder:
     """General radial feeder: depth-first branching tree (branching U{1..4})
-    or, with tree="recursive", a random recursive tree."""
+    or, with tree="recursive", a random recursive tree.  `zip_mix` gives every
+    load alpha = beta in {0, 1, 2} with probabilities (.6, .2, .2), drawn from a
+    separate stream so that everything else equals the constant-power feeder."""
     rng = np.random.default_rng([n_bus, seed, tag])
     if tree == "dfs":
         parent = dfs_branching_tree(n_bus, rng)
@@ -371,10 +374,12 @@ def make_radial(n_bus: int, seed: int, *, n_loads: int, load_mu_kw: float, load_
     n_loads = min(n_loads, n_bus - 1)
     buses = rng.choice(np.arange(1, n_bus), size=n_loads, replace=False)
     loads = []
+    rng_zip = np.random.default_rng([n_bus, seed, tag, 77])
     for b in buses:
         p = float(rng.lognormal(math.log(load_mu_kw), load_sigma))
         pf = rng.uniform(0.85, 0.98)
-        loads.append(make_load(int(b), phases[b], p, pf, "wye", 0.0, 0.0))
+        al = float(rng_zip.choice([0.0, 1.0, 2.0], p=[0.6, 0.2, 0.2])) if zip_mix else 0.0
+        loads.append(make_load(int(b), phases[b], p, pf, "wye", al, al))
     gens = [substation()]
     if n_der:
         der_buses = rng.choice(np.arange(1, n_bus), size=min(n_der, n_bus - 1), replace=False)
@@ -386,12 +391,13 @@ def make_radial(n_bus: int, seed: int, *, n_loads: int, load_mu_kw: float, load_
     return scale_for_voltage(f)
 
 
-def make_123bus(seed: int = 0) -> Feeder:
+def make_123bus(seed: int = 0, zip_mix: bool = False) -> Feeder:
     """123 buses on a random recursive tree, ~50% three-phase trunk, laterals
     60/40 one-/two-phase (30%/20% of all buses), 85 loads lognormal(ln 40 kW,
     0.6), 4 switchable DERs with capacity U[50, 200] kW, V_LL = 4.16 kV."""
     return make_radial(123, seed, n_loads=85, load_mu_kw=40.0, load_sigma=0.6, n_der=4,
-                       trunk_frac=0.5, p_single=0.6, v_ll_kv=4.16, name="123bus", tree="recursive")
+                       trunk_frac=0.5, p_single=0.6, v_ll_kv=4.16, name="123bus" + ("-zip" if zip_mix else ""),
+                       tree="recursive", zip_mix=zip_mix)
 
 
 def make_8500bus(seed: int = 0, n_bus: int = 8500) -> Feeder:
@@ -402,10 +408,12 @@ def make_8500bus(seed: int = 0, n_bus: int = 8500) -> Feeder:
                        name=f"{n_bus}bus")
 
 
-def make_2500bus(seed: int = 0) -> Feeder:
-    """One 2500-bus feeder as the 8500-bus generator, ~353 loads, no DERs."""
+def make_2500bus(seed: int = 0, zip_mix: bool = False) -> Feeder:
+    """One 2500-bus feeder as the 8500-bus generator, ~353 loads, no DERs
+    (with `zip_mix`, voltage-dependent loads as in make_radial)."""
     return make_radial(2500, seed, n_loads=353, load_mu_kw=5.0, load_sigma=0.8, n_der=0,
-                       trunk_frac=0.4, p_single=0.9, v_ll_kv=12.47, name="2500bus")
+                       trunk_frac=0.4, p_single=0.9, v_ll_kv=12.47, name="2500bus" + ("-zip" if zip_mix else ""),
+                       zip_mix=zip_mix)
 
 
 def scenario_load_factors(f: Feeder, k_scen: int, seed: int, sigma: float = 0.3) -> np.ndarray:
@@ -429,6 +437,10 @@ def by_name(name: str, seed: int = 0) -> Feeder:
         return make_8500bus(seed)
     if name in ("2500bus", "c4"):
         return make_2500bus(seed)
+    if name == "2500bus-zip":
+        return make_2500bus(seed, zip_mix=True)
+    if name == "123bus-zip":
+        return make_123bus(seed, zip_mix=True)
     if name.endswith("bus") and name[:-3].isdigit():
         return make_8500bus(seed, n_bus=int(name[:-3]))
     raise KeyError(name)

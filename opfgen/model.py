@@ -299,6 +299,45 @@ def scenario_rhs(inst: Instance, bus_factors: np.ndarray) -> np.ndarray:
     return out
 
 
+def scenario_zip(inst: Instance, bus_factors: np.ndarray):
+    """Load scenarios on one topology with voltage-dependent (ZIP) loads:
+    scenario k scales the reference powers of every load at bus i by
+    bus_factors[k, i].  In a load row (VDLM-1/2) both the right-hand side and
+    the coefficient on the bus voltage w are proportional to the reference
+    power, so a scenario changes b_s and those coefficients only.  Returns
+    (b_scen [K, sum m_s], a_pos [nv] flat positions into the stacked A values,
+    a_scen [K, nv] their values per scenario)."""
+    f = inst.feeder
+    base_b = np.concatenate([c.b for c in inst.comps])
+    K = bus_factors.shape[0]
+    b_scen = np.repeat(base_b[None, :], K, axis=0)
+    rows = inst.load_rows[:, 0]
+    buses = np.array([f.loads[l].bus for l in inst.load_rows[:, 1]], dtype=np.int64)
+    b_scen[:, rows] = base_b[rows][None, :] * bus_factors[:, buses]
+    # stacked row -> (component, local row); flat offset of each component's A
+    row_comp, row_local, a_off = [], [], []
+    off = 0
+    for s_, c in enumerate(inst.comps):
+        a_off.append(off)
+        off += c.A.size
+        row_comp.extend([s_] * c.A.shape[0])
+        row_local.extend(range(c.A.shape[0]))
+    pos, val_base, bus_of = [], [], []
+    for r, bus in zip(rows, buses):
+        s_ = row_comp[r]
+        c = inst.comps[s_]
+        i = row_local[r]
+        for j in range(c.A.shape[1]):
+            key = inst.var_keys[c.idx[j]]
+            if c.A[i, j] != 0.0 and key is not None and key[0] == "w":
+                pos.append(a_off[s_] + i * c.A.shape[1] + j)
+                val_base.append(c.A[i, j])
+                bus_of.append(bus)
+    a_pos = np.asarray(pos, dtype=np.int64)
+    a_scen = np.asarray(val_base)[None, :] * bus_factors[:, np.asarray(bus_of, dtype=np.int64)]
+    return b_scen, a_pos, a_scen
+
+
 def with_rhs(inst: Instance, b: np.ndarray) -> Instance:
     """A copy of the instance whose stacked right-hand side is b."""
     comps = []

@@ -37,7 +37,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBOUNDS", -3: "E
 
 EXPORTED = ["opf_admm_default_options", "opf_admm_setup", "opf_admm_solve", "opf_admm_run_fixed",
             "opf_admm_residuals", "opf_admm_get_info", "opf_admm_destroy", "opf_admm_last_error",
-            "opf_admm_setup_batch", "opf_admm_solve_batch", "opf_admm_batch_info", "opf_admm_destroy_batch",
+            "opf_admm_setup_batch", "opf_admm_setup_batch_ex", "opf_admm_solve_batch", "opf_admm_batch_info", "opf_admm_destroy_batch",
             "opf_admm_batch_last_error", "opf_server_default_options", "opf_server_create", "opf_server_submit",
             "opf_server_poll", "opf_server_get_stats", "opf_server_destroy", "opf_server_last_error"]
 
@@ -148,6 +148,10 @@ def load(path: str = LIB_PATH):
     lib.opf_admm_setup_batch.argtypes = [C.POINTER(opf_problem), C.POINTER(C.c_double), C.c_int32,
                                          C.POINTER(opf_admm_options), C.c_void_p, C.POINTER(H)]
     lib.opf_admm_setup_batch.restype = C.c_int
+    lib.opf_admm_setup_batch_ex.argtypes = [C.POINTER(opf_problem), C.POINTER(C.c_double), C.c_int32, C.c_int64,
+                                            C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                            C.POINTER(opf_admm_options), C.c_void_p, C.POINTER(H)]
+    lib.opf_admm_setup_batch_ex.restype = C.c_int
     lib.opf_admm_solve_batch.argtypes = [H, C.POINTER(opf_batch_result)]
     lib.opf_admm_solve_batch.restype = C.c_int
     lib.opf_admm_batch_info.argtypes = [H, C.POINTER(opf_admm_info)]
@@ -240,12 +244,22 @@ def opf_admm_last_error(h=None) -> str:
     return load().opf_admm_last_error(h).decode()
 
 
-def opf_admm_setup_batch(problem: opf_problem, b_scen: np.ndarray, options: opf_admm_options, stream: int = 0):
+def opf_admm_setup_batch(problem: opf_problem, b_scen: np.ndarray, options: opf_admm_options, stream: int = 0,
+                         a_pos=None, a_scen=None):
     lib = load()
     h = C.c_void_p()
     b = np.ascontiguousarray(b_scen, np.float64)
-    rc = lib.opf_admm_setup_batch(C.byref(problem), _ptr(b, C.c_double), int(b.shape[0]), C.byref(options),
-                                  C.c_void_p(stream or None), C.byref(h))
+    if a_pos is None:
+        rc = lib.opf_admm_setup_batch(C.byref(problem), _ptr(b, C.c_double), int(b.shape[0]), C.byref(options),
+                                      C.c_void_p(stream or None), C.byref(h))
+    else:
+        pos = np.ascontiguousarray(a_pos, np.int64)
+        val = np.ascontiguousarray(a_scen, np.float64)
+        if val.shape != (b.shape[0], pos.shape[0]):
+            raise ValueError("a_scen must be [K, len(a_pos)]")
+        rc = lib.opf_admm_setup_batch_ex(C.byref(problem), _ptr(b, C.c_double), int(b.shape[0]), int(pos.shape[0]),
+                                         _ptr(pos, C.c_int64), _ptr(val, C.c_double), C.byref(options),
+                                         C.c_void_p(stream or None), C.byref(h))
     if rc != OPF_OK:
         raise OpfError(rc, lib.opf_admm_batch_last_error(None).decode())
     return h
@@ -293,7 +307,8 @@ class BatchSolver:
     topology and A_s of the given problem arrays."""
 
     def __init__(self, n, c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx, b_scen, *, rho=100.0,
-                 eps_rel=1e-4, max_iter=1_000_000, check_every=64, split_terms=3, stream=0):
+                 eps_rel=1e-4, max_iter=1_000_000, check_every=64, split_terms=3, stream=0, a_pos=None,
+                 a_scen=None):
         keep = _keep(c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx)
         self.n = int(n)
         self.K = int(np.asarray(b_scen).shape[0])
@@ -303,7 +318,7 @@ class BatchSolver:
         o.max_iter = max_iter
         o.check_every = check_every
         o.split_terms = split_terms
-        self.h = opf_admm_setup_batch(_problem(keep, n), b_scen, o, stream)
+        self.h = opf_admm_setup_batch(_problem(keep, n), b_scen, o, stream, a_pos=a_pos, a_scen=a_scen)
 
     def close(self):
         if getattr(self, "h", None):

@@ -17,6 +17,8 @@
 //            the paper's dual-residual test at 1e-4;
 //   phase 3  z = Z + bbar, the dual update (ADMM-3) and per-scenario FP64
 //            residual partial sums.
+// Wavefronts of components whose A_s changes with the scenario (ZIP loads)
+// take phase 2 as a per-scenario product with their own FP32 factors instead.
 // A second launch reduces the partials per scenario, applies the termination
 // test per scenario and records each scenario's solution at its own stop
 // iteration; the batch runs until every scenario has stopped.
@@ -152,6 +154,22 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     f32x16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    const int vw = a.wave_var ? a.wave_var[w] : -1;
+    if (vw >= 0) {
+        // per-scenario factors: output (row r, scenario col) of this lane's
+        // sixteen tile positions, summed over the component's columns in order
+        const int col = 32 * nt + l32;
+        const size_t kk = (size_t)(kc + col);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int r = 32 * m + 8 * (v >> 2) + 4 * grp + (v & 3);
+            const int base = a.meta[(size_t)w * 64 + r] & 255;
+            const float* Fr = a.Fv + ((size_t)vw * a.fv_cols * 64 + r) * Kp + kk;
+            float z = 0.0f;
+            for (int j = 0; j < a.fv_cols; ++j) z = fmadd(Fr[(size_t)j * 64 * Kp], vs[(base + j) & 63][col], z);
+            acc[v] = z;
+        }
+    } else {
     const size_t plane = (size_t)a.W * 64 * 64;
     const uint16_t* Fw = a.Fp + (size_t)w * 64 * 64 + (size_t)(32 * m + l32) * 64;
 #pragma unroll
@@ -190,6 +208,7 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2, B2, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A3, B1, acc, 0, 0, 0);
         }
+    }
     }
 
     // ---- phase 3: z = Z + bbar, dual update, residual partials

@@ -232,6 +232,9 @@ struct BatchCtrl {
 struct BatchArgs {
     const uint16_t* Fp;     // [terms][W][64][64] bfloat16 planes of the block-diagonal factors
     int terms;              // 2 or 3
+    const int* wave_var;    // [W] index among the scenario-varying wavefronts or -1 (null: none)
+    const float* Fv;        // [varying wave][fv_cols][64][Kp] per-scenario factors (FP32)
+    int fv_cols;
     const int* var;
     const int* meta;        // base lane | n_s << 8 | owner << 16
     const int* cstart;

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -33,6 +34,9 @@ struct opf_admm_batch {
     double setup_ms = 0;
     std::string err;
     uint16_t* Fp = nullptr;
+    int* wave_var = nullptr;        // per wavefront: index among the scenario-varying wavefronts, or -1
+    float* Fv = nullptr;            // per-scenario factors of the varying wavefronts
+    int fv_cols = 0;
     int *var = nullptr, *meta = nullptr, *cstart = nullptr, *ccnt = nullptr, *clist = nullptr;
     float *lo = nullptr, *hi = nullptr, *cost = nullptr, *bbar = nullptr;
     float* z[2] = {nullptr, nullptr};
@@ -92,6 +96,7 @@ int bupload(opf_admm_batch* h, P** out, const std::vector<Q>& src) {
 
 void args_of(opf_admm_batch* h, BatchArgs& a, BatchRedArgs& r) {
     a.Fp = h->Fp; a.terms = h->terms;
+    a.wave_var = h->wave_var; a.Fv = h->Fv; a.fv_cols = h->fv_cols;
     a.var = h->var; a.meta = h->meta; a.cstart = h->cstart; a.ccnt = h->ccnt; a.clist = h->clist;
     a.lo = h->lo; a.hi = h->hi; a.cost = h->cost; a.bbar = h->bbar;
     a.z0 = h->z[0]; a.z1 = h->z[1]; a.l0 = h->l[0]; a.l1 = h->l[1]; a.x0 = h->x[0]; a.x1 = h->x[1];
@@ -110,9 +115,36 @@ extern "C" {
 
 int opf_admm_setup_batch(const opf_problem* p, const double* b_scen, int32_t K, const opf_admm_options* o,
                          void* hip_stream, opf_admm_batch** out) {
+    return opf_admm_setup_batch_ex(p, b_scen, K, 0, nullptr, nullptr, o, hip_stream, out);
+}
+
+int opf_admm_setup_batch_ex(const opf_problem* p, const double* b_scen, int32_t K, int64_t nv, const int64_t* a_pos,
+                            const double* a_scen, const opf_admm_options* o, void* hip_stream,
+                            opf_admm_batch** out) {
     if (out) *out = nullptr;
     if (!p || !b_scen || !out) return berr(nullptr, OPF_EINVAL, "null argument");
     if (K < 1 || K > 4096) return berr(nullptr, OPF_EINVAL, "K must be in [1, 4096]");
+    if (nv < 0 || (nv > 0 && (!a_pos || !a_scen))) return berr(nullptr, OPF_EINVAL, "bad scenario-varying A entries");
+    if (p->S < 1 || !p->comp_m || !p->comp_n || !p->A_vals) return berr(nullptr, OPF_EINVAL, "incomplete problem");
+    // components whose A_s changes with the scenario
+    std::vector<int64_t> aoff(p->S + 1, 0);
+    for (int q = 0; q < p->S; ++q) {
+        if (p->comp_m[q] < 0 || p->comp_n[q] < 1) return berr(nullptr, OPF_EINVAL, "bad component size");
+        aoff[q + 1] = aoff[q] + (int64_t)p->comp_m[q] * p->comp_n[q];
+    }
+    std::vector<int8_t> varying;
+    std::vector<int> pos_comp(nv);
+    if (nv > 0) {
+        varying.assign(p->S, 0);
+        for (int64_t j = 0; j < nv; ++j) {
+            if (a_pos[j] < 0 || a_pos[j] >= aoff[p->S]) return berr(nullptr, OPF_EINVAL, "A position out of range");
+            const int c = (int)(std::upper_bound(aoff.begin(), aoff.end(), a_pos[j]) - aoff.begin()) - 1;
+            pos_comp[j] = c;
+            varying[c] = 1;
+        }
+        for (int64_t q = 0; q < nv * K; ++q)
+            if (!std::isfinite(a_scen[q])) return berr(nullptr, OPF_EINVAL, "non-finite scenario A entry");
+    }
     opf_admm_options opt;
     if (o) opt = *o;
     else opf_admm_default_options(&opt);
@@ -130,11 +162,75 @@ int opf_admm_setup_batch(const opf_problem* p, const double* b_scen, int32_t K, 
     v.comp_m = p->comp_m; v.comp_n = p->comp_n; v.A = p->A_vals; v.b = p->b_vals ? p->b_vals : b_scen;
     v.idx = p->idx;
     h->lay.block_waves = 1;
+    h->lay.comp_group = varying;
     std::string err;
     const int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     int rc = build_layout(v, h->lay, err, threads);
     std::vector<float> bb;
-    if (!rc) rc = build_batch_rhs(v, h->lay, b_scen, K, h->Kp, bb, err, threads);
+    if (!rc) rc = build_batch_rhs(v, h->lay, b_scen, K, h->Kp, bb, err, threads, nv > 0 ? &varying : nullptr);
+    // per-scenario factors of the varying components (Section IV-B row
+    // reduction and closed_2 for each scenario's A_s), FP32, laid out
+    // [varying wave][column][lane][scenario]
+    std::vector<int> wave_var;
+    std::vector<float> Fv;
+    if (!rc && nv > 0) {
+        const HostLayout& L = h->lay;
+        std::vector<int64_t> ioff(p->S + 1, 0), boff(p->S + 1, 0);
+        for (int q = 0; q < p->S; ++q) {
+            ioff[q + 1] = ioff[q] + p->comp_n[q];
+            boff[q + 1] = boff[q] + p->comp_m[q];
+        }
+        wave_var.assign(L.waves, -1);
+        int nvw = 0;
+        for (int q = 0; q < p->S; ++q) {
+            if (!varying[q]) continue;
+            const int w = L.user_to_dev[ioff[q]] / 64;
+            if (wave_var[w] < 0) wave_var[w] = nvw++;
+            h->fv_cols = std::max(h->fv_cols, L.wave_maxn[w]);
+        }
+        std::vector<std::vector<int64_t>> cpos(p->S);   // varying entries of each component
+        for (int64_t j = 0; j < nv; ++j) cpos[pos_comp[j]].push_back(j);
+        const size_t Kp = (size_t)h->Kp, C = (size_t)h->fv_cols;
+        Fv.assign((size_t)nvw * C * 64 * Kp, 0.0f);
+        std::vector<int> vlist;
+        for (int q = 0; q < p->S; ++q)
+            if (varying[q]) vlist.push_back(q);
+        std::atomic<int> next(0), bad(-1);
+        const int64_t M = boff[p->S];
+        auto work = [&]() {
+            std::vector<double> A, F, bbar;
+            for (;;) {
+                const int t = next.fetch_add(1);
+                if (t >= (int)vlist.size() * K) break;
+                const int q = vlist[t / K], k = t % K;
+                const int m = p->comp_m[q], n = p->comp_n[q];
+                A.assign(p->A_vals + aoff[q], p->A_vals + aoff[q + 1]);
+                for (int64_t j : cpos[q]) A[a_pos[j] - aoff[q]] = a_scen[(size_t)k * nv + j];
+                F.assign((size_t)n * n, 0.0);
+                bbar.assign(n, 0.0);
+                int rank = 0;
+                if (component_factor(m, n, A.data(), b_scen + (size_t)k * M + boff[q], F.data(), bbar.data(), &rank)) {
+                    bad.store(q);
+                    continue;
+                }
+                const int d0 = L.user_to_dev[ioff[q]];
+                const int vw = wave_var[d0 / 64], base = d0 % 64;
+                for (int i = 0; i < n; ++i) {
+                    bb[(size_t)(d0 + i) * Kp + k] = (float)bbar[i];
+                    for (int jc = 0; jc < n; ++jc)
+                        Fv[(((size_t)vw * C + jc) * 64 + base + i) * Kp + k] = (float)F[(size_t)i * n + jc];
+                }
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int tt = 1; tt < threads; ++tt) pool.emplace_back(work);
+        work();
+        for (auto& th : pool) th.join();
+        if (bad.load() >= 0) {
+            rc = OPF_EINFEASIBLE_COMPONENT;
+            err = "a scenario's equations are inconsistent in component " + std::to_string(bad.load());
+        }
+    }
     if (rc) {
         delete h;
         return berr(nullptr, rc, err);
@@ -155,6 +251,10 @@ int opf_admm_setup_batch(const opf_problem* p, const double* b_scen, int32_t K, 
     std::vector<uint16_t> planes;
     build_dense_planes(L, h->terms, planes);
     if ((rc = bupload(h, &h->Fp, planes))) return fail(rc);
+    if (nv > 0) {
+        if ((rc = bupload(h, &h->wave_var, wave_var))) return fail(rc);
+        if ((rc = bupload(h, &h->Fv, Fv))) return fail(rc);
+    }
     if ((rc = bupload(h, &h->var, L.var))) return fail(rc);
     if ((rc = bupload(h, &h->meta, L.meta))) return fail(rc);
     if ((rc = bupload(h, &h->cstart, L.copy_start))) return fail(rc);

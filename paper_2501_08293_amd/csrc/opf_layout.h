@@ -37,6 +37,8 @@ struct HostLayout {
     int32_t max_ns = 0, max_copies = 0;
     int64_t sum_ns2 = 0;
     bool factors_on_device = false;   // input: leave F and bbar empty (computed by the device set-up)
+    std::vector<int8_t> comp_group;   // input (optional, per component): components of group 1 come
+                                      // first and never share a wavefront with group 0
 
     // per wavefront
     std::vector<int32_t> wave_maxn;   // columns stored for the wavefront
@@ -91,7 +93,8 @@ int component_rhs_map(int m, int n, const double* A, double* F, double* Wmap);
 // Batched scenarios sharing A: bbar of every slot and scenario in device order,
 // [slot][Kp] (scenario-minor, Kp >= K padded with zeros).  b_scen is [K][sum m_s].
 int build_batch_rhs(const ProblemView& p, const HostLayout& lay, const double* b_scen, int K, int Kp,
-                    std::vector<float>& out, std::string& err, int threads);
+                    std::vector<float>& out, std::string& err, int threads,
+                    const std::vector<int8_t>* skip = nullptr);
 
 // Dense block-diagonal 64 x 64 factor of every wavefront (row = output lane,
 // column = input lane), split into `terms` bfloat16 planes whose sum

@@ -257,6 +257,10 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
             }
         }
     }
+    // components of group 1 first (each group keeps its depth-first order)
+    const bool grouped = (int)out.comp_group.size() == S;
+    if (grouped)
+        std::stable_partition(order.begin(), order.end(), [&](int c2) { return out.comp_group[c2] == 1; });
     // ---- cut the order into workgroups of `block_waves` wavefronts; inside a
     // workgroup components are packed largest first with holes filled from the
     // small end, and a component never straddles two wavefronts
@@ -301,6 +305,7 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
             cur_lanes = 0;
         };
         for (int s2 : order) {
+            if (grouped && !cur.empty() && out.comp_group[cur.back()] != out.comp_group[s2]) emit();
             cur.push_back(s2);
             cur_lanes += p.comp_n[s2];
             if (cur_lanes > B * kWave * 3 / 4 && !pack(cur, ws)) {
@@ -425,7 +430,7 @@ int build_layout(const ProblemView& p, HostLayout& out, std::string& err, int th
 }
 
 int build_batch_rhs(const ProblemView& p, const HostLayout& lay, const double* b_scen, int K, int Kp,
-                    std::vector<float>& out, std::string& err, int threads) {
+                    std::vector<float>& out, std::string& err, int threads, const std::vector<int8_t>* skip) {
     const int S = p.S;
     std::vector<int64_t> aoff(S + 1), boff(S + 1), ioff(S + 1);
     aoff[0] = boff[0] = ioff[0] = 0;
@@ -445,6 +450,7 @@ int build_batch_rhs(const ProblemView& p, const HostLayout& lay, const double* b
             const int s = next.fetch_add(8);
             if (s >= S) break;
             for (int u = s; u < std::min(S, s + 8); ++u) {
+                if (skip && (*skip)[u]) continue;      // factored per scenario elsewhere
                 const int m = p.comp_m[u], n = p.comp_n[u];
                 F.assign((size_t)n * n, 0.0);
                 Wm.assign((size_t)n * std::max(m, 1), 0.0);

@@ -156,3 +156,31 @@ def test_scenario_rhs_equals_rebuilt_instance():
         inst2 = build_instance(f2)
         assert all(np.array_equal(c1.A, c2.A) for c1, c2 in zip(inst.comps, inst2.comps))
         np.testing.assert_allclose(np.concatenate([c.b for c in inst2.comps]), B[k], rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("name", ["13bus-zip", "123bus-zip"])
+def test_zip_scenarios_equal_rebuilt_instances(name):
+    """The ZIP scenario generator patches b and the load rows' w coefficients;
+    the result equals the instance rebuilt from the feeder with the loads of
+    every bus scaled by its factor (same component structure)."""
+    import copy
+    from opfgen import scenario_load_factors, scenario_zip
+    f = by_name(name, 0)
+    inst = build_instance(f)
+    assert any(np.any(ld.alpha != 0) for ld in f.loads)
+    fac = scenario_load_factors(f, 3, seed=5)
+    b_scen, a_pos, a_scen = scenario_zip(inst, fac)
+    assert len(a_pos) > 0
+    cm, cn, A, b, idx = inst.flat()
+    for k in range(3):
+        g = copy.deepcopy(f)
+        for ld in g.loads:
+            ld.a = ld.a * fac[k, ld.bus]
+            ld.b = ld.b * fac[k, ld.bus]
+        ref = build_instance(g)
+        cm2, cn2, A2, b2, idx2 = ref.flat()
+        assert np.array_equal(cm, cm2) and np.array_equal(cn, cn2) and np.array_equal(idx, idx2)
+        Ak = A.copy()
+        Ak[a_pos] = a_scen[k]
+        np.testing.assert_allclose(Ak, A2, rtol=1e-14, atol=0)
+        np.testing.assert_allclose(b_scen[k], b2, rtol=1e-14, atol=1e-300)
