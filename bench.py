@@ -283,7 +283,38 @@ def batch_leg(args, torch):
                  "frac": round(tf / BF16_DENSE_PEAK_TFLOPS, 5),
                  "useful_fraction_of_issued": round(useful_flops * 6 / max(mfma_flops, 1), 4)},
         "precision": "bf16 three-term split products on MFMA, fp32 accumulate, fp32 state, fp64 residual sums",
+        "zip_loads": zip_batch_timing(args, torch, K),
     }
+
+
+def zip_batch_timing(args, torch, K):
+    """The same batch with voltage-dependent (ZIP) loads: components whose
+    A_s change with the scenario run on per-scenario factors.  A fixed number
+    of iterations is timed (per-iteration cost against the shared path)."""
+    import numpy as np
+    from opfgen import build_instance, by_name, scenario_load_factors, scenario_zip
+    from paper_2501_08293_amd import BatchSolver
+    f = by_name(args.batch_workload + "-zip", args.seed)
+    inst = build_instance(f)
+    b_scen, a_pos, a_scen = scenario_zip(inst, scenario_load_factors(f, K, seed=1000))
+    st = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    s = BatchSolver(inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, *inst.flat(), b_scen=b_scen, rho=100.0,
+                    eps_rel=1e-12, max_iter=2048, check_every=256, stream=st.cuda_stream, a_pos=a_pos,
+                    a_scen=a_scen)
+    setup_s = time.perf_counter() - t0
+    s.solve()
+    t0 = time.perf_counter()
+    out = s.solve()
+    wall = time.perf_counter() - t0
+    s.close()
+    cm = inst.flat()[0]
+    cn = inst.flat()[1]
+    comp_of = np.searchsorted(np.cumsum(cm.astype(np.int64) * cn), a_pos, side="right")
+    return {"workload": f"{inst.name}: {K} scenarios, {len(a_pos)} scenario-varying A entries in "
+                        f"{len(np.unique(comp_of))} of {inst.S} components; 2048 iterations timed",
+            "setup_s": round(setup_s, 2),
+            "us_per_batch_iteration": round(1e6 * wall / max(int(out["total_iterations"]), 1), 2)}
 
 
 def serve_leg(args, torch):
