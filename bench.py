@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--serve-families", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--serve-eps", type=float, default=1e-3)
     ap.add_argument("--serve-chunk", type=int, default=256,
                     help="iterations each resident solve runs per shared launch")
@@ -321,7 +322,8 @@ def serve_leg(args, torch):
     import numpy as np
     from opfgen import build_instance, scenario_rhs
     from opfgen.serving import component_keys, make_family, poisson_arrivals, reconfigure
-    from paper_2501_08293_amd import Server, Solver
+    from paper_2501_08293_amd import OPF_PREC_FP64, OPF_PREC_MIXED, Server, Solver
+    prec = OPF_PREC_MIXED if args.serve_precision == "mixed" else OPF_PREC_FP64
     t0 = time.perf_counter()
     pool = []          # (family id, instance, component keys)
     for fid in range(args.serve_families):
@@ -345,7 +347,7 @@ def serve_leg(args, torch):
     # continuous batching through the serving runtime
     st = torch.cuda.Stream()
     srv = Server(rho=100.0, eps_rel=args.serve_eps, iters_per_poll=args.serve_chunk, arena_bytes=8 << 30,
-                 max_workgroups=16384, setup_threads=6, stream=st.cuda_stream)
+                 max_workgroups=16384, setup_threads=6, precision=prec, stream=st.cuda_stream)
     done = {}
     ids = {}
     t_start = time.perf_counter()
@@ -379,7 +381,7 @@ def serve_leg(args, torch):
         if wait > 0:
             time.sleep(wait)
         fid, inst, keys, arrs = reqs[i]
-        s = Solver(*arrs, rho=100.0, eps_rel=args.serve_eps, check_every=256, stream=st.cuda_stream)
+        s = Solver(*arrs, rho=100.0, eps_rel=args.serve_eps, check_every=256, precision=prec, stream=st.cuda_stream)
         r = s.solve()
         s.close()
         base_ok += int(r["status"] == 0)
@@ -401,6 +403,7 @@ def serve_leg(args, torch):
     return {
         "workload": f"{N} requests, Poisson {args.serve_rate:g}/s, {args.serve_families} feeder families "
                     f"(13-8500 buses log-uniform, tie-switch reconfigurations, fresh loads), eps_rel={args.serve_eps:g}",
+        "precision": "FP32 bulk + FP64 polish (both served and one at a time)" if prec == OPF_PREC_MIXED else "FP64",
         "solves_per_s": round(ok / span, 2),
         "p50_latency_ms": round(float(np.percentile(lat, 50)), 1),
         "p99_latency_ms": round(float(np.percentile(lat, 99)), 1),

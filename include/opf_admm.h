@@ -303,7 +303,9 @@ const char* opf_admm_batch_last_error(const opf_admm_batch* h);
 typedef struct opf_server opf_server;
 
 typedef struct opf_server_options {
-    opf_admm_options admm;     /* rho, eps_rel, max_iter of every solve */
+    opf_admm_options admm;     /* rho, eps_rel, max_iter, precision (OPF_PREC_FP64, or OPF_PREC_MIXED:
+                                  FP32 bulk phase in one launch, then FP64 polish in another, as the
+                                  single-instance solver does) and polish of every solve */
     int64_t arena_bytes;       /* device memory for resident solves (admission budget) */
     int64_t warm_bytes;        /* device memory for warm-start states (least recently used evicted) */
     int32_t max_slots;         /* most solves resident at once */
@@ -327,6 +329,7 @@ typedef struct opf_served {
     double  queue_ms;          /* submit -> admitted to the device */
     double  latency_ms;        /* submit -> result ready */
     double* x;                 /* the x buffer given at submit, now filled */
+    int64_t iterations_fp32;   /* of `iterations`, those of the FP32 bulk phase (mixed precision) */
 } opf_served;
 
 typedef struct opf_server_stats {

@@ -103,7 +103,8 @@ class opf_served(C.Structure):
     _fields_ = [("request_id", C.c_int64), ("status", C.c_int32), ("warm_components", C.c_int32),
                 ("iterations", C.c_int64), ("objective", C.c_double), ("pres", C.c_double),
                 ("dres", C.c_double), ("eps_prim", C.c_double), ("eps_dual", C.c_double),
-                ("queue_ms", C.c_double), ("latency_ms", C.c_double), ("x", C.c_void_p)]
+                ("queue_ms", C.c_double), ("latency_ms", C.c_double), ("x", C.c_void_p),
+                ("iterations_fp32", C.c_int64)]
 
 
 class opf_server_stats(C.Structure):
@@ -489,12 +490,16 @@ class Server:
     polled."""
 
     def __init__(self, *, rho=100.0, eps_rel=1e-4, max_iter=1_000_000, arena_bytes=4 << 30, warm_bytes=1 << 30,
-                 max_slots=256, max_workgroups=8192, iters_per_poll=256, setup_threads=4, warm_start=True, stream=0):
+                 max_slots=256, max_workgroups=8192, iters_per_poll=256, setup_threads=4, warm_start=True,
+                 precision=OPF_PREC_FP64, polish=True, spin_limit=0, stream=0):
         lib = load()
         o = opf_server_default_options()
         o.admm.rho = rho
         o.admm.eps_rel = eps_rel
         o.admm.max_iter = max_iter
+        o.admm.precision = precision
+        o.admm.polish = int(bool(polish))
+        o.admm.spin_limit = int(spin_limit)
         o.arena_bytes = int(arena_bytes)
         o.warm_bytes = int(warm_bytes)
         o.max_slots = max_slots
@@ -529,7 +534,8 @@ class Server:
         for i in range(max(k, 0)):
             r = buf[i]
             out.append(dict(request_id=r.request_id, status=r.status, warm_components=r.warm_components,
-                            iterations=r.iterations, objective=r.objective, pres=r.pres, dres=r.dres,
+                            iterations=r.iterations, iterations_fp32=r.iterations_fp32,
+                            objective=r.objective, pres=r.pres, dres=r.dres,
                             eps_prim=r.eps_prim, eps_dual=r.eps_dual, queue_ms=r.queue_ms,
                             latency_ms=r.latency_ms, x=self._pending.pop(r.request_id, None)))
         return out

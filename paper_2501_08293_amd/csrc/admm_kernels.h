@@ -167,6 +167,15 @@ struct InstDesc {
     double* z0; double* z1;
     double* l0; double* l1;
     double* x0; double* x1;
+    // FP32 copies for the bulk phase of a mixed-precision solve (null otherwise)
+    const float* Ff;
+    const float* bbarf;
+    const float* lof;
+    const float* hif;
+    const float* costf;
+    float* z0f; float* z1f;
+    float* l0f; float* l1f;
+    float* x0f; float* x1f;
     unsigned long long* records;// [kDecisionLag][10][blocks] tagged residual partial sums (word-major)
     unsigned long long* pub;    // [2][lanes][2] published copy terms (persistent schedule)
     long long* dec;             // [2]: last decided iteration, stop iteration
@@ -174,7 +183,6 @@ struct InstDesc {
     int blocks;                 // workgroups of this solve
     int lanes;                  // blocks * WPB * 64
     int n;
-    int lds_factors;            // 1: the factors of each workgroup fit the launch's LDS budget
     double rho, eps_rel;
 };
 
@@ -184,16 +192,21 @@ struct ServeArgs {
     long long spin_limit;
     long long chunk;            // iterations per launch before a solve pauses
     int xcd_remap;
-    int lds_cols;               // factor columns of the dynamic LDS budget per workgroup
+    int lds_cols;               // factor columns of the dynamic LDS budget per workgroup; a workgroup
+                                // whose factors fit holds them in LDS, the others read them from memory
 };
 
+// fp32 = 1: the launch runs the FP32 bulk phase of its solves, else FP64.  The
+// caller clears s.error before the launches of one round (a hang reported by
+// one launch makes the later ones of the round end early).
 hipError_t launch_serve_persistent(const InstDesc* descs, const int2* work, int nwork, const ServeArgs& s,
-                                   hipStream_t st);
-int serve_capacity(size_t lds_bytes);
+                                   int fp32, hipStream_t st);
+int serve_capacity(size_t lds_bytes, int fp32);
 
-hipError_t launch_multi_init(InstDesc* descs, int slot, int lanes, const double* z0, const double* l0,
-                             long long max_iter, hipStream_t st);
-hipError_t launch_multi_output(const InstDesc* descs, int slot, double* xo, double* zo, double* lo,
+// Control block reset; with narrow = 1 also the FP32 start state from the FP64 one.
+hipError_t launch_multi_init(InstDesc* descs, int slot, int lanes, long long max_iter, int narrow, hipStream_t st);
+// Outputs of the FP64 state, or (fp32 = 1) of the FP32 state of a solve that ends unpolished.
+hipError_t launch_multi_output(const InstDesc* descs, int slot, double* xo, double* zo, double* lo, int fp32,
                                hipStream_t st);
 hipError_t launch_warm_gather(const int4* plan, int nplan, const double* rz, const double* rl, double* zu,
                               double* lu, hipStream_t st);

@@ -7,14 +7,14 @@
 
 namespace opf {
 
-// Start state of one instance: z from (default start or warm values) in device
-// order, lambda likewise, control block reset.
-__global__ void multi_init_kernel(InstDesc* descs, int slot, const double* z0, const double* l0, long long max_iter) {
+// Control block of one instance reset for a new solve; with `narrow` the FP32
+// start state of the bulk phase is rounded from the FP64 start state.
+__global__ void multi_init_kernel(InstDesc* descs, int slot, long long max_iter, int narrow) {
     InstDesc& D = descs[slot];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < D.lanes && z0) {
-        D.z0[i] = z0[i];
-        D.l0[i] = l0 ? l0[i] : 0.0;
+    if (narrow && i < D.lanes) {
+        D.z0f[i] = (float)D.z0[i];
+        D.l0f[i] = (float)D.l0[i];
     }
     if (i == 0) {
         D.ctrl->iter = 0;
@@ -26,24 +26,31 @@ __global__ void multi_init_kernel(InstDesc* descs, int slot, const double* z0, c
     }
 }
 
-// Outputs of a finished instance in user order: x, and z / lambda (kept for
-// warm starts of later solves of the same feeder family).
-__global__ void multi_output_kernel(const InstDesc* descs, int slot, double* xo, double* zo, double* lo) {
-    const InstDesc& D = descs[slot];
+template <typename T>
+__device__ void write_outputs(const InstDesc& D, const T* z0, const T* z1, const T* l0, const T* l1, const T* x0,
+                              const T* x1, double* xo, double* zo, double* lo) {
     const long long t = D.ctrl->iter;
     const bool odd = (t & 1) != 0;
-    const double* zs = odd ? D.z1 : D.z0;
-    const double* ls = odd ? D.l1 : D.l0;
-    const double* xs = odd ? D.x1 : D.x0;
+    const T* zs = odd ? z1 : z0;
+    const T* ls = odd ? l1 : l0;
+    const T* xs = odd ? x1 : x0;
     const int gid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
     for (int d = gid; d < D.lanes; d += nth) {
         const int u = D.user_slot[d];
         if (u >= 0) {
-            zo[u] = zs[d];
-            lo[u] = ls[d];
+            zo[u] = (double)zs[d];
+            lo[u] = (double)ls[d];
         }
     }
-    for (int i = gid; i < D.n; i += nth) xo[i] = xs[i];
+    for (int i = gid; i < D.n; i += nth) xo[i] = (double)xs[i];
+}
+
+// Outputs of a finished instance in user order: x, and z / lambda (kept for
+// warm starts of later solves of the same feeder family).
+__global__ void multi_output_kernel(const InstDesc* descs, int slot, double* xo, double* zo, double* lo, int fp32) {
+    const InstDesc& D = descs[slot];
+    if (fp32) write_outputs<float>(D, D.z0f, D.z1f, D.l0f, D.l1f, D.x0f, D.x1f, xo, zo, lo);
+    else write_outputs<double>(D, D.z0, D.z1, D.l0, D.l1, D.x0, D.x1, xo, zo, lo);
 }
 
 // Copies warm-start values of matching components: for each pair
@@ -78,15 +85,14 @@ __global__ void to_device_order_kernel(const double* zu, const double* lu, const
     }
 }
 
-hipError_t launch_multi_init(InstDesc* descs, int slot, int lanes, const double* z0, const double* l0,
-                             long long max_iter, hipStream_t st) {
-    hipLaunchKernelGGL(multi_init_kernel, dim3((lanes + 255) / 256), dim3(256), 0, st, descs, slot, z0, l0, max_iter);
+hipError_t launch_multi_init(InstDesc* descs, int slot, int lanes, long long max_iter, int narrow, hipStream_t st) {
+    hipLaunchKernelGGL(multi_init_kernel, dim3((lanes + 255) / 256), dim3(256), 0, st, descs, slot, max_iter, narrow);
     return hipGetLastError();
 }
 
-hipError_t launch_multi_output(const InstDesc* descs, int slot, double* xo, double* zo, double* lo,
+hipError_t launch_multi_output(const InstDesc* descs, int slot, double* xo, double* zo, double* lo, int fp32,
                                hipStream_t st) {
-    hipLaunchKernelGGL(multi_output_kernel, dim3(64), dim3(256), 0, st, descs, slot, xo, zo, lo);
+    hipLaunchKernelGGL(multi_output_kernel, dim3(64), dim3(256), 0, st, descs, slot, xo, zo, lo, fp32);
     return hipGetLastError();
 }
 

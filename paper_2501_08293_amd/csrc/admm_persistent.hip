@@ -147,7 +147,7 @@ struct InstanceView {
     int hist_cap;
     int waves;
     int check;
-    int lds_factors;
+    int lds_factors;           // factor columns a workgroup may hold in LDS (0: none)
     T rho, inv_rho;
     double rho_d, eps_rel;
     long long max_iter;
@@ -311,10 +311,15 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
     // they fit (kept as a separate pointer so the loads stay LDS loads)
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     T* Fl = reinterpret_cast<T*>(dyn_lds);
-    const bool in_lds = a.lds_factors != 0;
+    // (decided per workgroup: the same for all its threads)
+    int off = 0, wg_cols = 0;
+    for (int q = 0; q < WPB; ++q) {
+        const int c = a.winfo[b * WPB + q].x;
+        off += q < wv ? c : 0;
+        wg_cols += c;
+    }
+    const bool in_lds = a.lds_factors > 0 && wg_cols <= a.lds_factors;
     if (in_lds) {
-        int off = 0;
-        for (int q = 0; q < wv; ++q) off += a.winfo[b * WPB + q].x;
         Fl += (size_t)off * 64;
         for (int k = 0; k < wi.x; ++k) Fl[k * 64 + lane] = Fg[k * 64 + lane];
     }
@@ -479,7 +484,7 @@ __device__ __forceinline__ InstanceView<T> view_of(const IterArgs<T>& a, const P
     v.z0 = a.z0; v.z1 = a.z1; v.l0 = a.l0; v.l1 = a.l1; v.x0 = a.x0; v.x1 = a.x1;
     v.pub = p.pub; v.records = p.records; v.dec_iter = p.dec_iter; v.dec_stop = p.dec_stop;
     v.ctrl = a.ctrl; v.hist = a.hist; v.hist_cap = a.hist_cap; v.waves = a.waves; v.check = p.check;
-    v.lds_factors = p.lds_factors; v.rho = a.rho; v.inv_rho = a.inv_rho; v.rho_d = a.rho_d;
+    v.lds_factors = p.lds_factors ? p.lds_factor_cols : 0; v.rho = a.rho; v.inv_rho = a.inv_rho; v.rho_d = a.rho_d;
     v.eps_rel = a.eps_rel; v.max_iter = p.max_iter; v.chunk = 0x3fffffffffffffffll;
     return v;
 }
@@ -495,48 +500,77 @@ __global__ __launch_bounds__(WPB * 64) void admm_persistent_kernel(IterArgs<T> a
 // list of (slot, workgroup of the solve; == blocks for its reducer).  Each
 // solve runs the single-instance persistent loop on its own state, for at
 // most `chunk` iterations, so every solve returns the same bits alone and in
-// any mix.
-__device__ __forceinline__ InstanceView<double> view_of(const InstDesc& D, const ServeArgs& s) {
-    InstanceView<double> v;
-    v.F = D.F; v.winfo = D.winfo; v.var = D.var; v.meta = D.meta; v.cstart = D.cstart; v.ccnt = D.ccnt;
-    v.clist = D.clist; v.bbar = D.bbar; v.lo = D.lo; v.hi = D.hi; v.cost = D.cost;
-    v.z0 = D.z0; v.z1 = D.z1; v.l0 = D.l0; v.l1 = D.l1; v.x0 = D.x0; v.x1 = D.x1;
+// any mix.  One launch runs one precision: the FP32 bulk phase of mixed
+// solves, or FP64 (plain solves and the polish phase).
+template <typename T>
+struct DescState;
+
+template <>
+struct DescState<double> {
+    static __device__ __forceinline__ void set(InstanceView<double>& v, const InstDesc& D) {
+        v.F = D.F; v.bbar = D.bbar; v.lo = D.lo; v.hi = D.hi; v.cost = D.cost;
+        v.z0 = D.z0; v.z1 = D.z1; v.l0 = D.l0; v.l1 = D.l1; v.x0 = D.x0; v.x1 = D.x1;
+    }
+    static __device__ __forceinline__ const double* z(const InstDesc& D, bool odd) { return odd ? D.z1 : D.z0; }
+    static __device__ __forceinline__ const double* l(const InstDesc& D, bool odd) { return odd ? D.l1 : D.l0; }
+};
+
+template <>
+struct DescState<float> {
+    static __device__ __forceinline__ void set(InstanceView<float>& v, const InstDesc& D) {
+        v.F = D.Ff; v.bbar = D.bbarf; v.lo = D.lof; v.hi = D.hif; v.cost = D.costf;
+        v.z0 = D.z0f; v.z1 = D.z1f; v.l0 = D.l0f; v.l1 = D.l1f; v.x0 = D.x0f; v.x1 = D.x1f;
+    }
+    static __device__ __forceinline__ const float* z(const InstDesc& D, bool odd) { return odd ? D.z1f : D.z0f; }
+    static __device__ __forceinline__ const float* l(const InstDesc& D, bool odd) { return odd ? D.l1f : D.l0f; }
+};
+
+template <typename T>
+__device__ __forceinline__ InstanceView<T> view_of(const InstDesc& D, const ServeArgs& s) {
+    InstanceView<T> v;
+    DescState<T>::set(v, D);
+    v.winfo = D.winfo; v.var = D.var; v.meta = D.meta; v.cstart = D.cstart; v.ccnt = D.ccnt; v.clist = D.clist;
     v.pub = D.pub; v.records = D.records; v.dec_iter = D.dec; v.dec_stop = D.dec + 1;
     v.ctrl = D.ctrl; v.hist = nullptr; v.hist_cap = 0; v.waves = D.lanes / 64; v.check = D.ctrl->check;
-    v.lds_factors = D.lds_factors; v.rho = D.rho; v.inv_rho = 1.0 / D.rho; v.rho_d = D.rho;
+    v.lds_factors = s.lds_cols; v.rho = (T)D.rho; v.inv_rho = (T)(1.0 / D.rho); v.rho_d = D.rho;
     v.eps_rel = D.eps_rel; v.max_iter = D.ctrl->max_iter; v.chunk = s.chunk;
     return v;
 }
 
 constexpr int kServeWPB = 4;
 
+template <typename T>
 __global__ __launch_bounds__(kServeWPB * 64) void admm_serve_kernel(const InstDesc* descs, const int2* work,
                                                                      ServeArgs s) {
     const int q = logical_block((int)blockIdx.x, (int)gridDim.x, s.xcd_remap);
     const int2 wk = work[q];
     const InstDesc& D = descs[wk.x];
     if (D.ctrl->stop) return;               // finished solves stay resident until retired
-    const InstanceView<double> v = view_of(D, s);
-    persistent_instance<double, kServeWPB>(v, wk.y, D.blocks, s.error, s.spin_limit);
+    const InstanceView<T> v = view_of<T>(D, s);
+    persistent_instance<T, kServeWPB>(v, wk.y, D.blocks, s.error, s.spin_limit);
 }
 
 // Before a serving launch: each work item prepares its own part of its solve
 // (published terms of the start iteration, residual records; the reducer item resets the
-// decisions); the first item clears the launch's error flag.
+// decisions).
+template <typename T>
 __global__ void serve_prepare_kernel(const InstDesc* descs, const int2* work) {
+    constexpr int W = Tag<T>::W;
     const int2 wk = work[blockIdx.x];
     const InstDesc& D = descs[wk.x];
     const long long t0 = D.ctrl->iter;
     const size_t LP = (size_t)D.lanes;
     if (wk.y < D.blocks) {
         const size_t d = (size_t)wk.y * blockDim.x + threadIdx.x;
-        const double z = (t0 & 1) ? D.z1[d] : D.z0[d];
-        const double l = (t0 & 1) ? D.l1[d] : D.l0[d];
-        u64 w[2];
-        Tag<double>::pack(copy_term(z, l, 1.0 / D.rho), (unsigned)t0, w);
-        for (int h = 0; h < 2; ++h) {
-            D.pub[d * 2 + h] = w[h];
-            D.pub[(LP + d) * 2 + h] = w[h];
+        const bool odd = (t0 & 1) != 0;
+        const T z = DescState<T>::z(D, odd)[d];
+        const T l = DescState<T>::l(D, odd)[d];
+        u64 w[W];
+        Tag<T>::pack(copy_term(z, l, (T)(1.0 / D.rho)), (unsigned)t0, w);
+#pragma unroll
+        for (int h = 0; h < W; ++h) {
+            D.pub[d * W + h] = w[h];
+            D.pub[(LP + d) * W + h] = w[h];
         }
         // residual records of this workgroup: tag t0 matches no iteration of the launch
         for (int q = threadIdx.x; q < kDecisionLag * kRec; q += blockDim.x)
@@ -547,27 +581,30 @@ __global__ void serve_prepare_kernel(const InstDesc* descs, const int2* work) {
     }
 }
 
-__global__ void clear_flag_kernel(int* f) { *f = 0; }
-
-hipError_t launch_serve_persistent(const InstDesc* descs, const int2* work, int nwork, const ServeArgs& s,
-                                   hipStream_t st) {
-    if (nwork < 1) return hipSuccess;
-    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, st, s.error);
-    hipLaunchKernelGGL(serve_prepare_kernel, dim3(nwork), dim3(kServeWPB * 64), 0, st, descs, work);
+template <typename T>
+hipError_t launch_serve(const InstDesc* descs, const int2* work, int nwork, const ServeArgs& s, hipStream_t st) {
+    hipLaunchKernelGGL(serve_prepare_kernel<T>, dim3(nwork), dim3(kServeWPB * 64), 0, st, descs, work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     ServeArgs sa = s;
     void* args[] = {(void*)&descs, (void*)&work, (void*)&sa};
-    const size_t lds = (size_t)s.lds_cols * 64 * sizeof(double);
-    return hipLaunchCooperativeKernel((const void*)admm_serve_kernel, dim3(nwork), dim3(kServeWPB * 64), args, lds, st);
+    const size_t lds = (size_t)s.lds_cols * 64 * sizeof(T);
+    return hipLaunchCooperativeKernel((const void*)admm_serve_kernel<T>, dim3(nwork), dim3(kServeWPB * 64), args,
+                                      lds, st);
 }
 
-int serve_capacity(size_t lds_bytes) {
+hipError_t launch_serve_persistent(const InstDesc* descs, const int2* work, int nwork, const ServeArgs& s, int fp32,
+                                   hipStream_t st) {
+    if (nwork < 1) return hipSuccess;
+    return fp32 ? launch_serve<float>(descs, work, nwork, s, st) : launch_serve<double>(descs, work, nwork, s, st);
+}
+
+int serve_capacity(size_t lds_bytes, int fp32) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_serve_kernel, kServeWPB * 64, lds_bytes) != hipSuccess)
-        return 0;
+    const void* k = fp32 ? (const void*)admm_serve_kernel<float> : (const void*)admm_serve_kernel<double>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kServeWPB * 64, lds_bytes) != hipSuccess) return 0;
     return per * cus;
 }
 

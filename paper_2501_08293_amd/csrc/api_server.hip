@@ -27,21 +27,33 @@
 #include "admm_kernels.h"
 #include "opf_layout.h"
 
+namespace opf {
+hipError_t launch_promote(const float* z32a, const float* z32b, const float* l32a, const float* l32b,
+                          double* z64a, double* z64b, double* l64a, double* l64b, int LP, Ctrl* ctrl,
+                          long long max_iter, int check, hipStream_t st);
+}  // namespace opf
+
 using namespace opf;
 
 namespace {
 
 using clk = std::chrono::steady_clock;
 constexpr int kWPB = 4;              // wavefronts per workgroup of the shared launch
-constexpr int kServeLdsCols = 96;    // factor columns per workgroup held in LDS (48 KiB in FP64)
+// factor columns per workgroup held in LDS: 48 KiB in either precision, so
+// that the launch stays register-bound at three workgroups per compute unit
+constexpr int kServeLdsCols64 = 96;
+constexpr int kServeLdsCols32 = 192;
 constexpr size_t kAlign = 256;
 
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Offsets of the arrays of one resident solve inside its arena region.
+// Offsets of the arrays of one resident solve inside its arena region (the
+// FP32 arrays only for mixed precision).
 struct Image {
     size_t winfo, var, meta, cstart, ccnt, clist, user_slot, F, bbar, lo, hi, cost, zdef, zdef_user;
-    size_t z0, z1, l0, l1, x0, x1, records, pub, dec, zu, lu, xo, plan, total;
+    size_t Ff, bbarf, lof, hif, costf;
+    size_t z0, z1, l0, l1, x0, x1, records, pub, dec, zu, lu, xo, plan;
+    size_t z0f, z1f, l0f, l1f, x0f, x1f, total;
 };
 
 struct Request {
@@ -59,7 +71,6 @@ struct Request {
     Image img{};
     std::vector<unsigned char> bytes;       // static part of the region image
     std::vector<int32_t> comp_off;          // user-order offset of each component
-    int lds_ok = 0;                         // every workgroup's factors fit the LDS budget
     clk::time_point t_submit, t_admit;
 };
 
@@ -77,6 +88,9 @@ struct Slot {
     size_t off = 0, len = 0;
     InstDesc desc{};
     int warm = 0;
+    int fp32 = 0;            // 1: in the FP32 bulk phase of a mixed-precision solve
+    int waiting = 0;         // 1: bulk phase done, waiting for room in the FP64 launch
+    long long it32 = 0;      // iterations of the bulk phase
 };
 
 // First-fit allocator over one device buffer (offsets).
@@ -117,7 +131,7 @@ struct Arena {
     }
 };
 
-Image plan_image(const HostLayout& L) {
+Image plan_image(const HostLayout& L, bool mixed) {
     Image im{};
     const size_t LP = (size_t)L.waves * kWave;
     size_t o = 0;
@@ -136,6 +150,12 @@ Image plan_image(const HostLayout& L) {
     im.cost = take(8 * LP);
     im.zdef = take(8 * LP);
     im.zdef_user = take(8 * (size_t)L.L);
+    const size_t h = mixed ? 1 : 0;
+    im.Ff = take(h * 4 * L.F.size());
+    im.bbarf = take(h * 4 * LP);
+    im.lof = take(h * 4 * LP);
+    im.hif = take(h * 4 * LP);
+    im.costf = take(h * 4 * LP);
     const size_t static_end = o;
     im.z0 = take(8 * LP);
     im.z1 = take(8 * LP);
@@ -150,6 +170,12 @@ Image plan_image(const HostLayout& L) {
     im.lu = take(8 * (size_t)L.L);
     im.xo = take(8 * (size_t)L.n);
     im.plan = take(16 * (size_t)L.S);
+    im.z0f = take(h * 4 * LP);
+    im.z1f = take(h * 4 * LP);
+    im.l0f = take(h * 4 * LP);
+    im.l1f = take(h * 4 * LP);
+    im.x0f = take(h * 4 * (size_t)L.n);
+    im.x1f = take(h * 4 * (size_t)L.n);
     im.total = o;
     (void)static_end;
     return im;
@@ -158,6 +184,12 @@ Image plan_image(const HostLayout& L) {
 template <typename T>
 void put(std::vector<unsigned char>& buf, size_t off, const std::vector<T>& v) {
     if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(T));
+}
+
+// FP32 copy (round to nearest) of an FP64 array.
+void put_narrow(std::vector<unsigned char>& buf, size_t off, const std::vector<double>& v) {
+    float* d = reinterpret_cast<float*>(buf.data() + off);
+    for (size_t i = 0; i < v.size(); ++i) d[i] = (float)v[i];
 }
 
 }  // namespace
@@ -173,12 +205,16 @@ struct opf_server {
     Ctrl* d_ctrls = nullptr;
     Ctrl* h_ctrls = nullptr;
     int2* h_work = nullptr;
+    int work_cap = 0;                      // entries of h_work / d_work
     int nwork = 0;
     int* d_error = nullptr;
     int* h_error = nullptr;
-    int capacity = 0;                      // co-resident workgroups of the serving kernel
+    bool mixed = false;                    // FP32 bulk phase + FP64 polish
+    int cap32 = 0, cap64 = 0;              // co-resident workgroups of the FP32 / FP64 serving kernel
     std::vector<Slot> slots;
-    int active = 0, active_blocks = 0;     // resident solves, their workgroups (reducers included)
+    int active = 0;                        // resident solves
+    int blocks32 = 0, blocks64 = 0;        // workgroups (reducers included) in the FP32 / FP64 launch
+    int nwork32 = 0;                       // the FP32 launch's items come first in the work list
     bool dirty = true;
     std::mutex mu;
     std::condition_variable cv_setup, cv_work, cv_result;
@@ -213,7 +249,7 @@ double ms_since(clk::time_point a, clk::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
-void push_result(opf_server* s, Request& r, int status, const Ctrl* c, int warm_comps) {
+void push_result(opf_server* s, Request& r, int status, const Ctrl* c, int warm_comps, long long it32 = 0) {
     opf_served o{};
     o.request_id = r.id;
     o.status = status;
@@ -224,6 +260,7 @@ void push_result(opf_server* s, Request& r, int status, const Ctrl* c, int warm_
     o.queue_ms = r.t_admit.time_since_epoch().count() ? ms_since(r.t_submit, r.t_admit) : o.latency_ms;
     if (c) {
         o.iterations = c->iter;
+        o.iterations_fp32 = it32;
         o.pres = c->res[0];
         o.dres = c->res[1];
         o.eps_prim = c->res[2];
@@ -259,7 +296,7 @@ void setup_loop(opf_server* s) {
         r->rc = build_layout(v, r->lay, r->err, 1);
         if (!r->rc) {
             const HostLayout& L = r->lay;
-            r->img = plan_image(L);
+            r->img = plan_image(L, s->mixed);
             if (r->img.total > s->arena.size) {
                 r->rc = OPF_ENOMEM;
                 r->err = "footprint larger than the arena";
@@ -285,13 +322,13 @@ void setup_loop(opf_server* s) {
                 for (size_t d = 0; d < L.user_slot.size(); ++d)
                     if (L.user_slot[d] >= 0) zu[L.user_slot[d]] = L.z0[d];
                 put(r->bytes, im.zdef_user, zu);
-                int cols = 0;
-                for (int b = 0; b < L.blocks; ++b) {
-                    int c = 0;
-                    for (int q = 0; q < kWPB; ++q) c += L.wave_maxn[(size_t)b * kWPB + q];
-                    cols = std::max(cols, c);
+                if (s->mixed) {
+                    put_narrow(r->bytes, im.Ff, L.F);
+                    put_narrow(r->bytes, im.bbarf, L.bbar);
+                    put_narrow(r->bytes, im.lof, L.lo);
+                    put_narrow(r->bytes, im.hif, L.hi);
+                    put_narrow(r->bytes, im.costf, L.cost);
                 }
-                r->lds_ok = cols <= kServeLdsCols;
                 r->comp_off.assign(r->S, 0);
                 for (int q = 1; q < r->S; ++q) r->comp_off[q] = r->comp_off[q - 1] + r->cn[q - 1];
             }
@@ -368,10 +405,22 @@ int admit_one(opf_server* s, std::unique_ptr<Request>& r, int slot_id) {
     D.l1 = reinterpret_cast<double*>(base + im.l1);
     D.x0 = reinterpret_cast<double*>(base + im.x0);
     D.x1 = reinterpret_cast<double*>(base + im.x1);
+    if (s->mixed) {
+        D.Ff = reinterpret_cast<const float*>(base + im.Ff);
+        D.bbarf = reinterpret_cast<const float*>(base + im.bbarf);
+        D.lof = reinterpret_cast<const float*>(base + im.lof);
+        D.hif = reinterpret_cast<const float*>(base + im.hif);
+        D.costf = reinterpret_cast<const float*>(base + im.costf);
+        D.z0f = reinterpret_cast<float*>(base + im.z0f);
+        D.z1f = reinterpret_cast<float*>(base + im.z1f);
+        D.l0f = reinterpret_cast<float*>(base + im.l0f);
+        D.l1f = reinterpret_cast<float*>(base + im.l1f);
+        D.x0f = reinterpret_cast<float*>(base + im.x0f);
+        D.x1f = reinterpret_cast<float*>(base + im.x1f);
+    }
     D.records = reinterpret_cast<unsigned long long*>(base + im.records);
     D.pub = reinterpret_cast<unsigned long long*>(base + im.pub);
     D.dec = reinterpret_cast<long long*>(base + im.dec);
-    D.lds_factors = q.lds_ok;
     D.ctrl = s->d_ctrls + slot_id;
     D.blocks = L.blocks;
     D.lanes = L.waves * kWave;
@@ -405,16 +454,19 @@ int admit_one(opf_server* s, std::unique_ptr<Request>& r, int slot_id) {
     }
     SHIPI(launch_to_device_order(zu, lu, D.user_slot, D.lanes, reinterpret_cast<const double*>(base + im.zdef),
                                 D.z0, D.l0, warm_comps > 0 ? 1 : 0, s->stream));
-    SHIPI(launch_multi_init(s->d_descs, slot_id, D.lanes, nullptr, nullptr, s->opt.admm.max_iter, s->stream));
+    SHIPI(launch_multi_init(s->d_descs, slot_id, D.lanes, s->opt.admm.max_iter, s->mixed ? 1 : 0, s->stream));
     sl.used = true;
     sl.off = off;
     sl.len = q.img.total;
     sl.desc = D;
     sl.warm = warm_comps;
+    sl.fp32 = s->mixed ? 1 : 0;
+    sl.waiting = 0;
+    sl.it32 = 0;
     q.t_admit = clk::now();
     sl.req = std::move(r);
     s->active++;
-    s->active_blocks += L.blocks + 1;
+    (s->mixed ? s->blocks32 : s->blocks64) += L.blocks + 1;
     s->dirty = true;
     return 1;
 }
@@ -430,13 +482,17 @@ bool admit_ready(opf_server* s) {
         for (int q = 0; q < (int)s->slots.size(); ++q)
             if (!s->slots[q].used) { free_slot = q; break; }
         const int need = r->lay.blocks + 1;        // compute workgroups + reducer
-        const int limit = std::min(s->opt.max_workgroups, s->capacity);
-        if (need > limit) {
+        // every phase of the solve must be able to run: the FP64 launch (plain
+        // solves, polish) and, for mixed precision, the FP32 launch
+        const int limit64 = std::min(s->opt.max_workgroups, s->cap64);
+        const int limit32 = std::min(s->opt.max_workgroups, s->cap32);
+        if (need > limit64 || (s->mixed && need > limit32)) {
             push_result(s, *r, OPF_ENOMEM, nullptr, 0);   // can never be co-resident on this device
             continue;
         }
+        const bool room = s->mixed ? s->blocks32 + need <= limit32 : s->blocks64 + need <= limit64;
         int rc = 0;
-        if (free_slot >= 0 && s->active_blocks + need <= limit)
+        if (free_slot >= 0 && room)
             rc = admit_one(s, r, free_slot);
         if (rc < 0) {
             push_result(s, *r, OPF_EHIP, nullptr, 0);   // device failure: report and drop
@@ -484,7 +540,7 @@ bool retire(opf_server* s, int slot_id) {
             lo = ws.l;
         }
     }
-    SHIP(launch_multi_output(s->d_descs, slot_id, xo, zo, lo, s->stream));
+    SHIP(launch_multi_output(s->d_descs, slot_id, xo, zo, lo, sl.fp32, s->stream));
     SHIP(hipMemcpyAsync(q.x_out, xo, 8 * (size_t)L.n, hipMemcpyDeviceToHost, s->stream));
     SHIP(hipStreamSynchronize(s->stream));
     if (keep) {
@@ -493,13 +549,63 @@ bool retire(opf_server* s, int slot_id) {
         s->warm_used += 16 * ws.L;
         s->warm[q.family] = std::move(ws);
     }
-    push_result(s, q, c.status, &c, sl.warm);
+    push_result(s, q, c.status, &c, sl.warm, sl.fp32 ? c.iter : sl.it32);
     s->arena.release(sl.off, sl.len);
     s->active--;
-    s->active_blocks -= L.blocks + 1;
+    if (!sl.waiting) (sl.fp32 ? s->blocks32 : s->blocks64) -= L.blocks + 1;
+    sl.waiting = 0;
     sl.used = false;
     sl.req.reset();
     s->dirty = true;
+    return true;
+}
+
+// A mixed-precision solve whose FP32 bulk phase has ended moves to the FP64
+// launch for the polish phase (the FP32 state of its last iteration widened,
+// as in the single-instance solver) once that launch has room; until then it
+// waits outside both launches.
+bool promote(opf_server* s, int q) {
+    Slot& sl = s->slots[q];
+    const InstDesc& D = sl.desc;
+    const int need = D.blocks + 1;
+    if (!sl.waiting) {
+        s->blocks32 -= need;
+        sl.it32 = s->h_ctrls[q].iter;
+        sl.waiting = 1;
+        s->dirty = true;
+    }
+    if (s->blocks64 + need > std::min(s->opt.max_workgroups, s->cap64)) return true;
+    SHIP(launch_promote(D.z0f, D.z1f, D.l0f, D.l1f, D.z0, D.z1, D.l0, D.l1, D.lanes, D.ctrl,
+                        sl.it32 + s->opt.admm.max_iter, 1, s->stream));
+    sl.fp32 = 0;
+    sl.waiting = 0;
+    s->blocks64 += need;
+    s->dirty = true;
+    return true;
+}
+
+// Work list: the FP32 launch's items, then the FP64 launch's.
+bool upload_work(opf_server* s) {
+    int nw = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int q = 0; q < (int)s->slots.size(); ++q) {
+            const Slot& sl = s->slots[q];
+            if (!sl.used || sl.waiting || sl.fp32 != (pass == 0 ? 1 : 0)) continue;
+            if (nw + sl.desc.blocks + 1 > s->work_cap) {
+                serr(s, OPF_EHIP, "work list overflow");
+                return false;
+            }
+            for (int b = 0; b <= sl.desc.blocks; ++b) s->h_work[nw++] = make_int2(q, b);
+        }
+        if (pass == 0) s->nwork32 = nw;
+    }
+    s->nwork = nw;
+    if (hipMemcpyAsync(s->d_work, s->h_work, sizeof(int2) * std::max(nw, 1), hipMemcpyHostToDevice, s->stream) !=
+        hipSuccess) {
+        serr(s, OPF_EHIP, "work list upload failed");
+        return false;
+    }
+    s->dirty = false;
     return true;
 }
 
@@ -509,7 +615,10 @@ void worker_loop(opf_server* s) {
     sa.spin_limit = s->opt.admm.spin_limit > 0 ? s->opt.admm.spin_limit : 4000000LL;
     sa.chunk = std::max(1, s->opt.iters_per_poll);
     sa.xcd_remap = s->opt.admm.workgroup_order == 1 ? 1 : 0;
-    sa.lds_cols = kServeLdsCols;
+    ServeArgs sa32 = sa;
+    sa.lds_cols = kServeLdsCols64;
+    sa32.lds_cols = kServeLdsCols32;
+    const bool polish = s->opt.admm.polish != 0;
     for (;;) {
         if (s->quit.load()) return;
         admit_ready(s);
@@ -519,22 +628,17 @@ void worker_loop(opf_server* s) {
                                 [&] { return s->quit.load() || !s->ready.empty(); });
             continue;
         }
-        if (s->dirty) {
-            int nw = 0;
-            for (int q = 0; q < (int)s->slots.size(); ++q) {
-                if (!s->slots[q].used) continue;
-                for (int b = 0; b <= s->slots[q].desc.blocks; ++b) s->h_work[nw++] = make_int2(q, b);
-            }
-            s->nwork = nw;
-            if (hipMemcpyAsync(s->d_work, s->h_work, sizeof(int2) * std::max(nw, 1), hipMemcpyHostToDevice,
-                               s->stream) != hipSuccess) {
-                serr(s, OPF_EHIP, "work list upload failed");
-                return;
-            }
-            s->dirty = false;
-        }
+        if (s->dirty && !upload_work(s)) return;
         const auto t0 = clk::now();
-        if (launch_serve_persistent(s->d_descs, s->d_work, s->nwork, sa, s->stream) != hipSuccess ||
+        const int n64 = s->nwork - s->nwork32;
+        // the two launches run one after the other on the stream; a hang in
+        // the first leaves the error flag set and the second ends early
+        bool ok = hipMemsetAsync(s->d_error, 0, sizeof(int), s->stream) == hipSuccess;
+        if (ok && s->nwork32 > 0)
+            ok = launch_serve_persistent(s->d_descs, s->d_work, s->nwork32, sa32, 1, s->stream) == hipSuccess;
+        if (ok && n64 > 0)
+            ok = launch_serve_persistent(s->d_descs, s->d_work + s->nwork32, n64, sa, 0, s->stream) == hipSuccess;
+        if (!ok ||
             hipMemcpyAsync(s->h_ctrls, s->d_ctrls, sizeof(Ctrl) * s->slots.size(), hipMemcpyDeviceToHost,
                            s->stream) != hipSuccess ||
             hipMemcpyAsync(s->h_error, s->d_error, sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
@@ -546,10 +650,19 @@ void worker_loop(opf_server* s) {
         s->launches += 1;
         const bool hang = *s->h_error != 0;
         for (int q = 0; q < (int)s->slots.size(); ++q) {
-            if (!s->slots[q].used) continue;
-            if (hang) s->h_ctrls[q].status = OPF_EHANG;     // a bounded wait ran out: end every resident solve
-            if (hang || s->h_ctrls[q].stop)
+            Slot& sl = s->slots[q];
+            if (!sl.used) continue;
+            if (hang) {
+                s->h_ctrls[q].status = OPF_EHANG;           // a bounded wait ran out: end every resident solve
                 if (!retire(s, q)) return;
+                continue;
+            }
+            if (!sl.waiting && !s->h_ctrls[q].stop) continue;
+            if (sl.fp32 && polish && s->h_ctrls[q].status != OPF_ENUMERIC) {
+                if (!promote(s, q)) return;
+            } else if (!sl.waiting) {
+                if (!retire(s, q)) return;
+            }
         }
     }
 }
@@ -578,7 +691,8 @@ int opf_server_create(const opf_server_options* o, void* hip_stream, opf_server*
     if (o) opt = *o;
     else opf_server_default_options(&opt);
     if (!(opt.admm.rho > 0) || !(opt.admm.eps_rel > 0) || opt.admm.max_iter < 1 || opt.arena_bytes < (1 << 20) ||
-        opt.max_slots < 1 || opt.max_workgroups < 1 || opt.iters_per_poll < 1)
+        opt.max_slots < 1 || opt.max_workgroups < 1 || opt.iters_per_poll < 1 ||
+        (opt.admm.precision != OPF_PREC_FP64 && opt.admm.precision != OPF_PREC_MIXED))
         return serr(nullptr, OPF_EINVAL, "invalid server options");
     auto s = std::make_unique<opf_server>();
     s->opt = opt;
@@ -596,7 +710,8 @@ int opf_server_create(const opf_server_options* o, void* hip_stream, opf_server*
     };
     if (hipMalloc((void**)&s->arena_base, (size_t)opt.arena_bytes) != hipSuccess) return fail(OPF_ENOMEM, "arena allocation failed");
     s->arena.init((size_t)opt.arena_bytes);
-    const int MS = opt.max_slots, MW = opt.max_workgroups;
+    // work list: up to max_workgroups items in each of the two launches of a round
+    const int MS = opt.max_slots, MW = 2 * opt.max_workgroups;
     if (hipMalloc((void**)&s->d_descs, sizeof(InstDesc) * MS) != hipSuccess ||
         hipMalloc((void**)&s->d_work, sizeof(int2) * MW) != hipSuccess ||
         hipMalloc((void**)&s->d_error, sizeof(int)) != hipSuccess ||
@@ -606,13 +721,17 @@ int opf_server_create(const opf_server_options* o, void* hip_stream, opf_server*
         hipHostMalloc((void**)&s->h_work, sizeof(int2) * MW, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&s->h_error, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return fail(OPF_ENOMEM, "pinned allocation failed");
+    s->work_cap = MW;
     *s->h_error = 0;
     if (hipMemsetAsync(s->d_error, 0, sizeof(int), s->stream) != hipSuccess ||
         hipMemsetAsync(s->d_ctrls, 0, sizeof(Ctrl) * MS, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return fail(OPF_EHIP, "device initialisation failed");
-    s->capacity = serve_capacity((size_t)kServeLdsCols * 64 * sizeof(double));
-    if (s->capacity < 2) return fail(OPF_EHIP, "the serving kernel cannot be resident on this device");
+    s->mixed = opt.admm.precision == OPF_PREC_MIXED;
+    s->cap64 = serve_capacity((size_t)kServeLdsCols64 * 64 * sizeof(double), 0);
+    s->cap32 = s->mixed ? serve_capacity((size_t)kServeLdsCols32 * 64 * sizeof(float), 1) : 0;
+    if (s->cap64 < 2 || (s->mixed && s->cap32 < 2))
+        return fail(OPF_EHIP, "the serving kernel cannot be resident on this device");
     s->slots.resize(MS);
     opf_server* raw = s.release();
     for (int t = 0; t < raw->opt.setup_threads; ++t) raw->setup_threads.emplace_back(setup_loop, raw);

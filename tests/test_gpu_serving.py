@@ -1,10 +1,14 @@
 """Serving runtime: continuous batching of independent solves.
 
 Checks: a solve returns the same bits alone and in a mix of other solves (and
-the same bits as the single-instance step kernel with the same workgroup
-shape); results match the FP64 oracle; admission respects the arena
-footprint and rejects a solve larger than the arena; warm starts from the
-resident state of the same family reduce iterations and keep the accuracy."""
+the same bits as the single-instance persistent solve with the same workgroup
+shape), in FP64 and in mixed precision (FP32 bulk launch, FP64 polish launch),
+also when some of its workgroups exceed the launch's LDS budget; results match
+the FP64 oracle, also under admission limits that make solves queue for
+either launch; admission respects the arena footprint and rejects a solve
+larger than the arena; warm starts from the resident state of the same family
+reduce iterations and keep the accuracy; bounded waits that run out end the
+round's solves with OPF_EHANG and the device stays usable."""
 import sys
 import time
 
@@ -122,3 +126,99 @@ def test_warm_start_from_resident_family_state():
     ref = admm.solve(admm.setup(nxt), rho=RHO, eps_rel=1e-8)
     assert abs(res1["objective"] - ref.objective) <= 2e-4 * abs(ref.objective)
     assert abs(resc["objective"] - ref.objective) <= 2e-4 * abs(ref.objective)
+
+
+def test_mixed_precision_serving_equals_single_instance_mixed(mix):
+    """FP32 bulk phase in the FP32 launch, FP64 polish in the FP64 launch: each
+    served solve returns the bits (iterations of both phases, x) of the
+    single-instance mixed-precision persistent solve, in a mix and alone, with
+    and without polish."""
+    from paper_2501_08293_amd import OPF_PREC_MIXED, Server, Solver
+    for polish in (True, False):
+        _say(f"[gpu] serving mixed precision, polish={polish}: mix vs single-instance")
+        srv = Server(rho=RHO, eps_rel=1e-4, warm_start=False, iters_per_poll=32, arena_bytes=256 << 20,
+                     precision=OPF_PREC_MIXED, polish=polish)
+        ids = [srv.submit(*_args(inst), family=k) for k, inst in enumerate(mix)]
+        res = _drain(srv, ids)
+        srv.close()
+        for k, inst in enumerate(mix):
+            r = res[ids[k]]
+            s = Solver(*_args(inst), rho=RHO, eps_rel=1e-4, kernel=1, block_waves=4, precision=OPF_PREC_MIXED,
+                       polish=polish)
+            one = s.solve()
+            s.close()
+            assert r["status"] == 0 and one["status"] == 0
+            assert r["iterations"] == one["iterations"] and r["iterations_fp32"] == one["iterations_fp32"]
+            assert r["iterations_fp32"] > 0
+            if not polish:
+                assert r["iterations"] == r["iterations_fp32"]
+            assert np.array_equal(r["x"], one["x"]), k
+        srv = Server(rho=RHO, eps_rel=1e-4, warm_start=False, iters_per_poll=16, arena_bytes=64 << 20,
+                     precision=OPF_PREC_MIXED, polish=polish)
+        rid = srv.submit(*_args(mix[2]))
+        ra = _drain(srv, [rid])[rid]
+        srv.close()
+        assert ra["iterations"] == res[ids[2]]["iterations"] and np.array_equal(ra["x"], res[ids[2]]["x"])
+
+
+def test_mixed_precision_serving_matches_oracle_under_tight_admission(mix):
+    """With room for a single 123-bus solve per launch, solves queue for the
+    FP32 launch and for the FP64 polish launch; results keep the bits of the
+    unconstrained mix and agree with the FP64 oracle to 1e-4 in the objective."""
+    from paper_2501_08293_amd import OPF_PREC_MIXED, Server
+    _say("[gpu] serving mixed precision, 16 workgroups per launch, vs oracle")
+    kw = dict(rho=RHO, eps_rel=1e-4, warm_start=False, iters_per_poll=32, arena_bytes=256 << 20,
+              precision=OPF_PREC_MIXED)
+    srv = Server(max_workgroups=16, **kw)
+    ids = [srv.submit(*_args(inst), family=k) for k, inst in enumerate(mix)]
+    res = _drain(srv, ids)
+    srv.close()
+    free = Server(**kw)
+    fids = [free.submit(*_args(inst), family=k) for k, inst in enumerate(mix)]
+    fres = _drain(free, fids)
+    free.close()
+    for k, inst in enumerate(mix):
+        r = res[ids[k]]
+        assert r["status"] == 0
+        assert r["iterations"] == fres[fids[k]]["iterations"] and np.array_equal(r["x"], fres[fids[k]]["x"])
+        ref = admm.solve(admm.setup(inst), rho=RHO, eps_rel=1e-4)
+        assert abs(r["objective"] - ref.objective) <= 1e-4 * abs(ref.objective)
+
+
+def test_serving_bounded_wait_reports_ehang_and_recovers(mix):
+    """A spin limit of one poll (forced from the host; every wait still ends)
+    makes bounded waits run out: every solve of the round is answered with
+    OPF_EHANG or a normal result, and a new server then solves normally."""
+    from paper_2501_08293_amd import OPF_PREC_MIXED, Server
+    _say("[gpu] serving forced wait timeout, mixed precision")
+    srv = Server(rho=RHO, eps_rel=1e-4, warm_start=False, iters_per_poll=32, arena_bytes=256 << 20,
+                 precision=OPF_PREC_MIXED, spin_limit=1)
+    ids = [srv.submit(*_args(inst), family=k) for k, inst in enumerate(mix[:3])]
+    res = _drain(srv, ids)
+    srv.close()
+    assert all(res[i]["status"] in (0, -8) for i in ids)
+    srv = Server(rho=RHO, eps_rel=1e-4, warm_start=False, iters_per_poll=32, arena_bytes=256 << 20,
+                 precision=OPF_PREC_MIXED)
+    rid = srv.submit(*_args(mix[2]))
+    r = _drain(srv, [rid])[rid]
+    srv.close()
+    assert r["status"] == 0
+
+
+def test_workgroups_over_the_lds_budget_keep_the_bits():
+    """A 254-bus feeder whose largest workgroups hold more factor columns (110)
+    than the FP64 serving launch keeps in LDS (96): those workgroups read their
+    factors from memory, the others from LDS, and the solve returns the bits of
+    the single-instance persistent solve (all factors in LDS)."""
+    from paper_2501_08293_amd import Server, Solver
+    _say("[gpu] serving: per-workgroup LDS budget, 254-bus feeder, FP64")
+    inst = build_instance(make_family(0, 0).base)
+    srv = Server(rho=RHO, eps_rel=1e-3, warm_start=False, iters_per_poll=256, arena_bytes=256 << 20)
+    rid = srv.submit(*_args(inst))
+    r = _drain(srv, [rid])[rid]
+    srv.close()
+    s = Solver(*_args(inst), rho=RHO, eps_rel=1e-3, kernel=1, block_waves=4)
+    one = s.solve()
+    s.close()
+    assert r["status"] == 0 and one["status"] == 0
+    assert r["iterations"] == one["iterations"] and np.array_equal(r["x"], one["x"])
