@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--serve-eps", type=float, default=1e-3)
-    ap.add_argument("--serve-chunk", type=int, default=256,
+    ap.add_argument("--serve-chunk", type=int, default=512,
                     help="iterations each resident solve runs per shared launch")
     ap.add_argument("--only", choices=["batch", "serve"], default=None,
                     help="run only this leg and print its record (for profiling runs)")
