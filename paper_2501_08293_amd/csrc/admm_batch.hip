@@ -56,8 +56,11 @@ __device__ __forceinline__ double wave_sum_b(double v) {
     return v;
 }
 
-// grid (W, Kp / 64), 256 threads: wavefront w of the packing, scenarios
-// [64 * blockIdx.y, 64 * blockIdx.y + 64)
+// grid W * Kp / 64, 256 threads: workgroup (wavefront w of the packing,
+// scenarios [kc, kc + 64)); each XCD runs a contiguous range of packing
+// positions, so the copies of a variable (in nearby wavefronts) and the four
+// scenario tiles of one factor tile meet in one L2.  LDS 36.6 KiB: four
+// workgroups per compute unit.
 __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     if (a.ctrl->stop) return;
     const long long t = a.ctrl->iter + 1;
@@ -70,12 +73,13 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     const size_t Kp = (size_t)a.Kp;
 
     __shared__ float xs[64][65];      // [slot][scenario]
-    __shared__ float vs[64][65];
-    __shared__ double red[4][5][32];
+    __shared__ __align__(16) float vs[64][65];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int w = blockIdx.x;
-    const int kc = blockIdx.y * 64;
+    const int KB = a.Kp >> 6;
+    const int pos = logical_block((int)blockIdx.x, (int)gridDim.x, 1);
+    const int w = pos / KB;
+    const int kc = (pos - w * KB) * 64;
 
     // ---- slot descriptors of this wavefront staged in LDS (one load per thread)
     __shared__ int s_var[64], s_cn[64], s_cs[64], s_owner[64];
@@ -211,6 +215,10 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     }
     }
 
+    // the V tile is dead once every wave has its products: its LDS holds the
+    // residual partials
+    __syncthreads();
+    double (*red)[5][32] = reinterpret_cast<double (*)[5][32]>(&vs[0][0]);
     // ---- phase 3: z = Z + bbar, dual update, residual partials
     // D[row][col] of a 32 x 32 tile: col = lane % 32, row = 8 (v / 4) + 4 (lane / 32) + v % 4
     const int col = 32 * nt + l32;
@@ -220,7 +228,7 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     for (int v = 0; v < 16; ++v) {
         const int r = 32 * m + 8 * (v >> 2) + 4 * grp + (v & 3);
         const size_t d = (size_t)w * 64 + r;
-        if (a.var[d] >= 0) {
+        if (s_var[r] >= 0) {
             const float zn = acc[v] + a.bbar[d * Kp + kk];
             const float xv = xs[r][col];
             const float zo = zp[d * Kp + kk];
@@ -342,7 +350,7 @@ __global__ void batch_init_kernel(const double* z0, float* z, float* l, int LP, 
 }
 
 hipError_t launch_batch_iteration(const BatchArgs& a, const BatchRedArgs& r, hipStream_t st) {
-    hipLaunchKernelGGL(admm_batch_step_kernel, dim3(a.W, a.Kp / 64), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(admm_batch_step_kernel, dim3(a.W * (a.Kp / 64)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(admm_batch_reduce_kernel, dim3(r.K), dim3(256), 0, st, r);
     return hipGetLastError();
 }

@@ -150,6 +150,17 @@ struct PersistArgs {
 // history each slot keeps in registers).
 constexpr int kDecisionLag = 3;
 
+// Position of a workgroup in the packing.  With remap, hardware workgroup ids
+// (dealt round-robin over the 8 XCDs) are renumbered so that each XCD runs a
+// contiguous range of the packing (a permutation of [0, nb)): neighbouring
+// workgroups then share data through one XCD's L2.
+__device__ __forceinline__ int logical_block(int bx, int nb, int remap) {
+    if (!remap) return bx;
+    const int x = bx & 7, j = bx >> 3;
+    const int full = nb >> 3, rem = nb & 7;
+    return x * full + (x < rem ? x : rem) + j;
+}
+
 // ---- serving runtime: one resident solve (see admm_multi.hip, admm_persistent.hip)
 struct InstDesc {
     const int2* winfo;

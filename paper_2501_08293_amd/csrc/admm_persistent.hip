@@ -109,17 +109,6 @@ constexpr int kCopyRegs = 8;
 constexpr int kBatch = 3;      // workgroups whose records a reducer thread loads at once
 constexpr int kRec = 10;       // words of one residual record (5 doubles, two tagged halves each)
 
-// Position of this workgroup in the packing.  With xcd_remap, hardware
-// workgroup ids (dealt round-robin over the 8 XCDs) are renumbered so that
-// each XCD runs a contiguous range of the packing: neighbouring workgroups
-// then exchange their terms inside one XCD.
-__device__ __forceinline__ int logical_block(int bx, int nb, int remap) {
-    if (!remap) return bx;
-    const int x = bx & 7, j = bx >> 3;
-    const int full = nb >> 3, rem = nb & 7;
-    return x * full + (x < rem ? x : rem) + j;
-}
-
 // Everything one solve's persistent loop touches, for the single-instance
 // kernel and for each solve of the serving kernel.
 template <typename T>
