@@ -1,0 +1,64 @@
+// Batched same-topology scenarios (internal header; see admm_batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace opf {
+
+// ---- batched same-topology scenarios (see admm_batch.hip)
+struct BatchCtrl {
+    long long iter;         // completed iterations
+    long long max_iter;
+    int stop;               // 1: every scenario has stopped (later launches return)
+    int done;               // scenarios stopped so far
+    unsigned arrive;        // last-workgroup counter of the reduction launch
+    int pad;
+};
+
+struct BatchArgs {
+    const uint16_t* Fp;     // [terms][W][64][64] bfloat16 planes of the block-diagonal factors
+    int terms;              // 2 or 3
+    const int* wave_var;    // [W] index among the scenario-varying wavefronts or -1 (null: none)
+    const float* Fv;        // [varying wave][fv_cols][64][Kp] per-scenario factors (FP32)
+    int fv_cols;
+    int vary_waves;         // the varying wavefronts lie in [0, vary_waves) of the packing (0: none)
+    const int* var;
+    const int* meta;        // base lane | n_s << 8 | owner << 16
+    const int* cstart;
+    const int* ccnt;
+    const int* clist;
+    const float* lo;
+    const float* hi;
+    const float* cost;
+    const float* bbar;      // [LP][Kp]
+    float* z0; float* z1;   // [LP][Kp] ping-pong
+    float* l0; float* l1;
+    float* x0; float* x1;   // [n][Kp]
+    double* part;           // [5][Kp][W] per-wavefront residual partials
+    BatchCtrl* ctrl;
+    int W, Kp, K, n;
+    float rho, inv_rho;
+};
+
+struct BatchRedArgs {
+    const double* part;
+    BatchCtrl* ctrl;
+    int* state;             // [K] 0 running, 1 converged, 2 stopped at max_iter, 3 NaN/Inf
+    long long* iters;       // [K]
+    double* res;            // [K][4]
+    double* objective;      // [K]
+    double* xout;           // [K][n] snapshot at the scenario's stop iteration
+    const float* x0; const float* x1;
+    const double* c;
+    int W, Kp, K, n;
+    double rho, eps_rel;
+};
+
+
+hipError_t launch_batch_iteration(const BatchArgs& a, const BatchRedArgs& r, hipStream_t st);
+hipError_t launch_batch_init(const double* z0, float* z, float* l, int LP, int Kp, BatchCtrl* ctrl, int* state,
+                             int K, long long max_iter, hipStream_t st);
+
+}  // namespace opf

@@ -27,6 +27,7 @@
 #include <cstdint>
 
 #include "../../include/opf_admm.h"
+#include "admm_batch.h"
 #include "admm_kernels.h"
 
 namespace opf {
@@ -59,8 +60,9 @@ __device__ __forceinline__ double wave_sum_b(double v) {
 // grid W * Kp / 64, 256 threads: workgroup (wavefront w of the packing,
 // scenarios [kc, kc + 64)); each XCD runs a contiguous range of packing
 // positions, so the copies of a variable (in nearby wavefronts) and the four
-// scenario tiles of one factor tile meet in one L2.  LDS 36.6 KiB: four
-// workgroups per compute unit.
+// scenario tiles of one factor tile meet in one L2.  The workgroups of the
+// scenario-varying wavefronts (the slowest, packed first) are dealt over all
+// XCDs and start first.  LDS 36.6 KiB: four workgroups per compute unit.
 __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     if (a.ctrl->stop) return;
     const long long t = a.ctrl->iter + 1;
@@ -77,7 +79,8 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int KB = a.Kp >> 6;
-    const int pos = logical_block((int)blockIdx.x, (int)gridDim.x, 1);
+    const int nvb = a.vary_waves * KB, bx = (int)blockIdx.x;
+    const int pos = bx < nvb ? bx : nvb + logical_block(bx - nvb, (int)gridDim.x - nvb, 1);
     const int w = pos / KB;
     const int kc = (pos - w * KB) * 64;
 

@@ -224,76 +224,4 @@ hipError_t launch_warm_gather(const int4* plan, int nplan, const double* rz, con
 hipError_t launch_to_device_order(const double* zu, const double* lu, const int* user_slot, int lanes,
                                   const double* zdef, double* zd, double* ld, int use_warm, hipStream_t st);
 
-// ---- device set-up of the component factors (see setup_device.hip)
-struct FactorJob {
-    const double* A;          // concatenated row-major m_s x n_s blocks
-    const double* b;          // concatenated m_s entries
-    const int64_t* aoff;      // [S]
-    const int64_t* boff;      // [S]
-    const int* comp_m;        // [S]
-    const int* comp_n;        // [S]
-    const int* comp_dev;      // [S] first device slot of the component
-    const int64_t* wave_foff; // [waves] element offset of each wave's factor block
-    double* F;                // packed factors (zeroed before the launch)
-    double* bbar;             // [lanes]
-    int* status;              // [S] 0 or OPF_EINFEASIBLE_COMPONENT
-    int S;
-};
-size_t factor_lds_bytes(int m, int n);
-hipError_t launch_factors(const FactorJob& job, size_t lds_bytes, hipStream_t st);
-hipError_t launch_narrow(const double* src, float* dst, int64_t count, hipStream_t st);
-
-// ---- batched same-topology scenarios (see admm_batch.hip)
-struct BatchCtrl {
-    long long iter;         // completed iterations
-    long long max_iter;
-    int stop;               // 1: every scenario has stopped (later launches return)
-    int done;               // scenarios stopped so far
-    unsigned arrive;        // last-workgroup counter of the reduction launch
-    int pad;
-};
-
-struct BatchArgs {
-    const uint16_t* Fp;     // [terms][W][64][64] bfloat16 planes of the block-diagonal factors
-    int terms;              // 2 or 3
-    const int* wave_var;    // [W] index among the scenario-varying wavefronts or -1 (null: none)
-    const float* Fv;        // [varying wave][fv_cols][64][Kp] per-scenario factors (FP32)
-    int fv_cols;
-    const int* var;
-    const int* meta;        // base lane | n_s << 8 | owner << 16
-    const int* cstart;
-    const int* ccnt;
-    const int* clist;
-    const float* lo;
-    const float* hi;
-    const float* cost;
-    const float* bbar;      // [LP][Kp]
-    float* z0; float* z1;   // [LP][Kp] ping-pong
-    float* l0; float* l1;
-    float* x0; float* x1;   // [n][Kp]
-    double* part;           // [5][Kp][W] per-wavefront residual partials
-    BatchCtrl* ctrl;
-    int W, Kp, K, n;
-    float rho, inv_rho;
-};
-
-struct BatchRedArgs {
-    const double* part;
-    BatchCtrl* ctrl;
-    int* state;             // [K] 0 running, 1 converged, 2 stopped at max_iter, 3 NaN/Inf
-    long long* iters;       // [K]
-    double* res;            // [K][4]
-    double* objective;      // [K]
-    double* xout;           // [K][n] snapshot at the scenario's stop iteration
-    const float* x0; const float* x1;
-    const double* c;
-    int W, Kp, K, n;
-    double rho, eps_rel;
-};
-
-
-hipError_t launch_batch_iteration(const BatchArgs& a, const BatchRedArgs& r, hipStream_t st);
-hipError_t launch_batch_init(const double* z0, float* z, float* l, int LP, int Kp, BatchCtrl* ctrl, int* state,
-                             int K, long long max_iter, hipStream_t st);
-
 }  // namespace opf

@@ -136,7 +136,8 @@ struct InstanceView {
     int hist_cap;
     int waves;
     int check;
-    int lds_factors;           // factor columns a workgroup may hold in LDS (0: none)
+    int lds_factors;           // 0: factors read from memory; otherwise 1 (every workgroup's factors
+                               // fit the launch's LDS), or with per-workgroup checks the column budget
     T rho, inv_rho;
     double rho_d, eps_rel;
     long long max_iter;
@@ -257,7 +258,10 @@ __device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int*
 
 // The persistent loop of one solve for workgroup b of its G compute
 // workgroups (b == G: its reducer).
-template <typename T, int WPB>
+// PER_WG_LDS: each workgroup checks its own factor columns against the LDS
+// budget (serving, where one launch holds several solves); otherwise the
+// budget covers every workgroup of the launch.
+template <typename T, int WPB, bool PER_WG_LDS>
 __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int* error, long long spin_limit) {
     constexpr int NT = WPB * 64;
     constexpr int W = Tag<T>::W;
@@ -300,15 +304,16 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
     // they fit (kept as a separate pointer so the loads stay LDS loads)
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     T* Fl = reinterpret_cast<T*>(dyn_lds);
-    // (decided per workgroup: the same for all its threads)
-    int off = 0, wg_cols = 0;
-    for (int q = 0; q < WPB; ++q) {
-        const int c = a.winfo[b * WPB + q].x;
-        off += q < wv ? c : 0;
-        wg_cols += c;
+    // (the same decision for all threads of the workgroup)
+    bool in_lds = a.lds_factors != 0;
+    if (PER_WG_LDS) {
+        int wg_cols = 0;
+        for (int q = 0; q < WPB; ++q) wg_cols += a.winfo[b * WPB + q].x;
+        in_lds = in_lds && wg_cols <= a.lds_factors;
     }
-    const bool in_lds = a.lds_factors > 0 && wg_cols <= a.lds_factors;
     if (in_lds) {
+        int off = 0;
+        for (int q = 0; q < wv; ++q) off += a.winfo[b * WPB + q].x;
         Fl += (size_t)off * 64;
         for (int k = 0; k < wi.x; ++k) Fl[k * 64 + lane] = Fg[k * 64 + lane];
     }
@@ -473,7 +478,7 @@ __device__ __forceinline__ InstanceView<T> view_of(const IterArgs<T>& a, const P
     v.z0 = a.z0; v.z1 = a.z1; v.l0 = a.l0; v.l1 = a.l1; v.x0 = a.x0; v.x1 = a.x1;
     v.pub = p.pub; v.records = p.records; v.dec_iter = p.dec_iter; v.dec_stop = p.dec_stop;
     v.ctrl = a.ctrl; v.hist = a.hist; v.hist_cap = a.hist_cap; v.waves = a.waves; v.check = p.check;
-    v.lds_factors = p.lds_factors ? p.lds_factor_cols : 0; v.rho = a.rho; v.inv_rho = a.inv_rho; v.rho_d = a.rho_d;
+    v.lds_factors = p.lds_factors; v.rho = a.rho; v.inv_rho = a.inv_rho; v.rho_d = a.rho_d;
     v.eps_rel = a.eps_rel; v.max_iter = p.max_iter; v.chunk = 0x3fffffffffffffffll;
     return v;
 }
@@ -482,7 +487,7 @@ template <typename T, int WPB>
 __global__ __launch_bounds__(WPB * 64) void admm_persistent_kernel(IterArgs<T> a, PersistArgs p) {
     const InstanceView<T> v = view_of(a, p);
     const int b = logical_block((int)blockIdx.x, (int)gridDim.x, p.xcd_remap);
-    persistent_instance<T, WPB>(v, b, (int)gridDim.x - 1, p.error, p.spin_limit);
+    persistent_instance<T, WPB, false>(v, b, (int)gridDim.x - 1, p.error, p.spin_limit);
 }
 
 // Serving: the launch's workgroups are dealt to the resident solves by a work
@@ -536,7 +541,7 @@ __global__ __launch_bounds__(kServeWPB * 64) void admm_serve_kernel(const InstDe
     const InstDesc& D = descs[wk.x];
     if (D.ctrl->stop) return;               // finished solves stay resident until retired
     const InstanceView<T> v = view_of<T>(D, s);
-    persistent_instance<T, kServeWPB>(v, wk.y, D.blocks, s.error, s.spin_limit);
+    persistent_instance<T, kServeWPB, true>(v, wk.y, D.blocks, s.error, s.spin_limit);
 }
 
 // Before a serving launch: each work item prepares its own part of its solve

@@ -14,6 +14,7 @@
 
 #include "../../include/opf_admm.h"
 #include "admm_kernels.h"
+#include "setup_device.h"
 #include "opf_layout.h"
 
 namespace opf {

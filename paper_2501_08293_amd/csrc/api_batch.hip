@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/opf_admm.h"
+#include "admm_batch.h"
 #include "admm_kernels.h"
 #include "opf_layout.h"
 
@@ -37,6 +38,7 @@ struct opf_admm_batch {
     int* wave_var = nullptr;        // per wavefront: index among the scenario-varying wavefronts, or -1
     float* Fv = nullptr;            // per-scenario factors of the varying wavefronts
     int fv_cols = 0;
+    int vary_waves = 0;             // end of the prefix of wavefronts holding the varying components
     int *var = nullptr, *meta = nullptr, *cstart = nullptr, *ccnt = nullptr, *clist = nullptr;
     float *lo = nullptr, *hi = nullptr, *cost = nullptr, *bbar = nullptr;
     float* z[2] = {nullptr, nullptr};
@@ -96,7 +98,7 @@ int bupload(opf_admm_batch* h, P** out, const std::vector<Q>& src) {
 
 void args_of(opf_admm_batch* h, BatchArgs& a, BatchRedArgs& r) {
     a.Fp = h->Fp; a.terms = h->terms;
-    a.wave_var = h->wave_var; a.Fv = h->Fv; a.fv_cols = h->fv_cols;
+    a.wave_var = h->wave_var; a.Fv = h->Fv; a.fv_cols = h->fv_cols; a.vary_waves = h->vary_waves;
     a.var = h->var; a.meta = h->meta; a.cstart = h->cstart; a.ccnt = h->ccnt; a.clist = h->clist;
     a.lo = h->lo; a.hi = h->hi; a.cost = h->cost; a.bbar = h->bbar;
     a.z0 = h->z[0]; a.z1 = h->z[1]; a.l0 = h->l[0]; a.l1 = h->l[1]; a.x0 = h->x[0]; a.x1 = h->x[1];
@@ -187,6 +189,7 @@ int opf_admm_setup_batch_ex(const opf_problem* p, const double* b_scen, int32_t 
             const int w = L.user_to_dev[ioff[q]] / 64;
             if (wave_var[w] < 0) wave_var[w] = nvw++;
             h->fv_cols = std::max(h->fv_cols, L.wave_maxn[w]);
+            h->vary_waves = std::max(h->vary_waves, w + 1);
         }
         std::vector<std::vector<int64_t>> cpos(p->S);   // varying entries of each component
         for (int64_t j = 0; j < nv; ++j) cpos[pos_comp[j]].push_back(j);

@@ -19,6 +19,7 @@
 
 #include "../../include/opf_admm.h"
 #include "admm_kernels.h"
+#include "setup_device.h"
 
 namespace opf {
 
