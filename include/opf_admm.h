@@ -56,6 +56,14 @@ extern "C" {
 #define OPF_PREC_FP64   0   /* factors, state, residuals all FP64 */
 #define OPF_PREC_MIXED  1   /* FP32 factors/state in the bulk phase, FP64 residual sums,
                                then FP64 polish iterations until the FP64 test holds */
+/* With polish and eps_rel below OPF_MIXED_STALL_BELOW, the FP32 bulk phase
+   also ends when it stalls at its rounding level: every
+   OPF_MIXED_STALL_WINDOW iterations the ratio max(pres/eps_prim, dres/eps_dual)
+   is compared with its value at the previous check, and unless it has at
+   least halved, the solve goes on to the FP64 polish.  Serving applies the
+   same checks at the same iterations when iters_per_poll divides the window. */
+#define OPF_MIXED_STALL_BELOW  1e-5
+#define OPF_MIXED_STALL_WINDOW 65536
 
 /* ---- kernel schedule ----------------------------------------------------- */
 #define OPF_KERNEL_AUTO        0

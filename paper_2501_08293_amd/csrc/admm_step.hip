@@ -291,6 +291,11 @@ hipError_t launch_promote(const float* z32a, const float* z32b, const float* l32
     return hipGetLastError();
 }
 
+hipError_t launch_rearm(Ctrl* ctrl, long long max_iter, int check, hipStream_t st) {
+    hipLaunchKernelGGL(rearm_kernel, dim3(1), dim3(64), 0, st, ctrl, max_iter, check);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_output(const T* z0, const T* z1, const T* l0, const T* l1, const T* x0, const T* x1,
                          const int* user_slot, int LP, int n, const double* c, double* xo, double* zo,

@@ -25,6 +25,7 @@ hipError_t launch_init(const double* z0, const double* lam0, T* z, T* l, int LP,
 hipError_t launch_promote(const float* z32a, const float* z32b, const float* l32a, const float* l32b,
                           double* z64a, double* z64b, double* l64a, double* l64b, int LP, Ctrl* ctrl,
                           long long max_iter, int check, hipStream_t st);
+hipError_t launch_rearm(Ctrl* ctrl, long long max_iter, int check, hipStream_t st);
 template <typename T>
 hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G, hipStream_t st);
 template <typename T> int persistent_capacity(int wpb, size_t lds_bytes);
@@ -392,9 +393,24 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
     h->ctrl_host->iter = 0;
     r->kernel_ms_fp32 = 0;
     if (h->opt.precision == OPF_PREC_MIXED) {
-        HIPCHK(launch_init<float>(z0, l0, h->s32.z[0], h->s32.l[0], h->LP, h->ctrl, max_iter, check, h->stream));
-        rc = run_any<float>(h, h->s32, &h->graph32, max_iter, check);
+        // below OPF_MIXED_STALL_BELOW the bulk phase runs in windows and ends
+        // early when the residual ratio stops halving from window to window
+        const bool watch = h->opt.polish && !fixed && h->opt.eps_rel < OPF_MIXED_STALL_BELOW;
+        long long stop_at = watch ? std::min<long long>(OPF_MIXED_STALL_WINDOW, max_iter) : max_iter;
+        HIPCHK(launch_init<float>(z0, l0, h->s32.z[0], h->s32.l[0], h->LP, h->ctrl, stop_at, check, h->stream));
+        rc = run_any<float>(h, h->s32, &h->graph32, stop_at, check);
         if (rc) return rc;
+        double q_prev = HUGE_VAL;
+        while (watch && h->ctrl_host->status == OPF_NOT_CONVERGED && h->ctrl_host->iter < max_iter) {
+            const Ctrl& c = *h->ctrl_host;
+            const double q = std::max(c.res[0] / c.res[2], c.res[1] / c.res[3]);
+            if (!(q < 0.5 * q_prev)) break;          // stalled: on to the polish
+            q_prev = q;
+            stop_at = std::min<long long>(c.iter + OPF_MIXED_STALL_WINDOW, max_iter);
+            HIPCHK(launch_rearm(h->ctrl, stop_at, check, h->stream));
+            rc = run_any<float>(h, h->s32, &h->graph32, stop_at, check);
+            if (rc) return rc;
+        }
         it32 = h->ctrl_host->iter;
         status = h->ctrl_host->status;
         r->kernel_ms_fp32 = h->kernel_ms;

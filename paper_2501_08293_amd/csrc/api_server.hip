@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -91,6 +92,8 @@ struct Slot {
     int fp32 = 0;            // 1: in the FP32 bulk phase of a mixed-precision solve
     int waiting = 0;         // 1: bulk phase done, waiting for room in the FP64 launch
     long long it32 = 0;      // iterations of the bulk phase
+    double q_prev = 0;       // stall watch of the bulk phase: residual ratio at the last check
+    long long next_check = 0;
 };
 
 // First-fit allocator over one device buffer (offsets).
@@ -463,6 +466,8 @@ int admit_one(opf_server* s, std::unique_ptr<Request>& r, int slot_id) {
     sl.fp32 = s->mixed ? 1 : 0;
     sl.waiting = 0;
     sl.it32 = 0;
+    sl.q_prev = HUGE_VAL;
+    sl.next_check = OPF_MIXED_STALL_WINDOW;
     q.t_admit = clk::now();
     sl.req = std::move(r);
     s->active++;
@@ -619,6 +624,7 @@ void worker_loop(opf_server* s) {
     sa.lds_cols = kServeLdsCols64;
     sa32.lds_cols = kServeLdsCols32;
     const bool polish = s->opt.admm.polish != 0;
+    const bool watch = s->mixed && polish && s->opt.admm.eps_rel < OPF_MIXED_STALL_BELOW;
     for (;;) {
         if (s->quit.load()) return;
         admit_ready(s);
@@ -657,7 +663,16 @@ void worker_loop(opf_server* s) {
                 if (!retire(s, q)) return;
                 continue;
             }
-            if (!sl.waiting && !s->h_ctrls[q].stop) continue;
+            const Ctrl& c = s->h_ctrls[q];
+            bool stalled = false;
+            if (watch && sl.fp32 && !sl.waiting && !c.stop && c.iter >= sl.next_check) {
+                // the bulk phase's stall watch, as in the single-instance solver
+                const double r = std::max(c.res[0] / c.res[2], c.res[1] / c.res[3]);
+                if (!(r < 0.5 * sl.q_prev)) stalled = true;
+                sl.q_prev = r;
+                sl.next_check += OPF_MIXED_STALL_WINDOW;
+            }
+            if (!sl.waiting && !c.stop && !stalled) continue;
             if (sl.fp32 && polish && s->h_ctrls[q].status != OPF_ENUMERIC) {
                 if (!promote(s, q)) return;
             } else if (!sl.waiting) {

@@ -164,6 +164,28 @@ def test_mixed_precision_matches_fp64_oracle(kernel):
     s.close()
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_mixed_precision_stall_hands_over_to_the_polish(kernel):
+    """eps_rel = 1e-9 is below what FP32 iterates resolve on this feeder: the
+    bulk phase's stall watch (every 65536 iterations the residual ratio must
+    halve) ends it at a window boundary instead of at max_iter, and the FP64
+    polish meets the FP64 test at 1e-9; the objective agrees with the FP64
+    oracle solved to the same tolerance within 1e-7 relative (the 1e-8 and
+    1e-9 oracle optima differ by 5e-8)."""
+    from paper_2501_08293_amd import OPF_PREC_MIXED
+    _say(f"[gpu] mixed precision at eps_rel 1e-9, 13bus kernel={kernel}")
+    inst = _inst("13bus")
+    s = _solver(inst, rho=RHO, eps_rel=1e-9, precision=OPF_PREC_MIXED, kernel=kernel)
+    out = s.solve()
+    s.close()
+    assert out["status"] == 0
+    assert 0 < out["iterations_fp32"] < out["iterations"]
+    assert out["iterations_fp32"] % 65536 == 0 and out["iterations_fp32"] <= 4 * 65536
+    assert out["pres"] <= out["eps_prim"] and out["dres"] <= out["eps_dual"]
+    ref = admm.solve(_oracle("13bus"), rho=RHO, eps_rel=1e-9)
+    assert abs(out["objective"] - ref.objective) <= 1e-7 * abs(ref.objective)
+
+
 def test_device_outputs_and_warm_start_from_torch():
     import torch
     _say("[gpu] torch device buffers 13bus")

@@ -222,3 +222,26 @@ def test_workgroups_over_the_lds_budget_keep_the_bits():
     s.close()
     assert r["status"] == 0 and one["status"] == 0
     assert r["iterations"] == one["iterations"] and np.array_equal(r["x"], one["x"])
+
+
+def test_mixed_precision_serving_stall_watch(mix):
+    """eps_rel = 1e-9: the served bulk phase is ended by the stall watch at the
+    same window boundary as in the single-instance solver, and the polish in
+    the FP64 launch reaches 1e-9 with the bits of the single-instance mixed
+    solve."""
+    from paper_2501_08293_amd import OPF_PREC_MIXED, Server, Solver
+    _say("[gpu] serving mixed precision at eps_rel 1e-9")
+    srv = Server(rho=RHO, eps_rel=1e-9, warm_start=False, iters_per_poll=64, arena_bytes=64 << 20,
+                 precision=OPF_PREC_MIXED)
+    ids = [srv.submit(*_args(inst), family=k) for k, inst in enumerate(mix[:2])]
+    res = _drain(srv, ids)
+    srv.close()
+    for k, inst in enumerate(mix[:2]):
+        r = res[ids[k]]
+        s = Solver(*_args(inst), rho=RHO, eps_rel=1e-9, kernel=1, block_waves=4, precision=OPF_PREC_MIXED)
+        one = s.solve()
+        s.close()
+        assert r["status"] == 0 and 0 < r["iterations_fp32"] < r["iterations"]
+        assert r["pres"] <= r["eps_prim"] and r["dres"] <= r["eps_dual"]
+        assert r["iterations"] == one["iterations"] and r["iterations_fp32"] == one["iterations_fp32"]
+        assert np.array_equal(r["x"], one["x"])
