@@ -24,12 +24,20 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Arrival counters of the step kernel: workgroup b arrives on counter
+// b % kArriveGroups, and the last arrival of each group on ctrl->arrive, so
+// that no single address takes one atomic per workgroup.  They live after the
+// residual partials: [G][5] doubles, 16 doubles of slack, then the counters.
+constexpr int kArriveGroups = 32;
+__host__ __device__ constexpr size_t step_partials_doubles(size_t G) { return G * 5 + 16 + kArriveGroups / 2; }
+
 // Residual sums of a workgroup -> global partials; the last workgroup reduces
 // them and writes the control block.  All threads of the block must call it.
 template <int NT>
 __device__ __forceinline__ void finish_iteration(const double (&s)[5], double* partials, Ctrl* ctrl,
                                                  double* hist, int hist_cap, long long t,
                                                  double rho, double eps_rel) {
+    unsigned* grp = reinterpret_cast<unsigned*>(partials + (size_t)gridDim.x * 5 + 16);
     __shared__ double red[NT / 64][5];
     __shared__ int is_last;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -55,8 +63,19 @@ __device__ __forceinline__ void finish_iteration(const double (&s)[5], double* p
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        const unsigned old = __hip_atomic_fetch_add(&ctrl->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (old == gridDim.x - 1);
+        const unsigned ng = gridDim.x < (unsigned)kArriveGroups ? gridDim.x : (unsigned)kArriveGroups;
+        const unsigned gi = blockIdx.x % ng;
+        const unsigned in_group = (gridDim.x - gi + ng - 1) / ng;
+        const unsigned og = __hip_atomic_fetch_add(&grp[gi], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int last = 0;
+        if (og == in_group - 1) {
+            // last of its group: every member's partials are complete; the
+            // counter returns to 0 for the next iteration (a later launch)
+            __hip_atomic_store(&grp[gi], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned old = __hip_atomic_fetch_add(&ctrl->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = (old == ng - 1);
+        }
+        is_last = last;
     }
     __syncthreads();
     if (!is_last) return;
@@ -290,6 +309,8 @@ hipError_t launch_promote(const float* z32a, const float* z32b, const float* l32
     hipLaunchKernelGGL(rearm_kernel, dim3(1), dim3(64), 0, st, ctrl, max_iter, check);
     return hipGetLastError();
 }
+
+size_t step_partials_count(int G) { return step_partials_doubles((size_t)G); }
 
 hipError_t launch_rearm(Ctrl* ctrl, long long max_iter, int check, hipStream_t st) {
     hipLaunchKernelGGL(rearm_kernel, dim3(1), dim3(64), 0, st, ctrl, max_iter, check);

@@ -26,6 +26,7 @@ hipError_t launch_promote(const float* z32a, const float* z32b, const float* l32
                           double* z64a, double* z64b, double* l64a, double* l64b, int LP, Ctrl* ctrl,
                           long long max_iter, int check, hipStream_t st);
 hipError_t launch_rearm(Ctrl* ctrl, long long max_iter, int check, hipStream_t st);
+size_t step_partials_count(int G);
 template <typename T>
 hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G, hipStream_t st);
 template <typename T> int persistent_capacity(int wpb, size_t lds_bytes);
@@ -626,7 +627,10 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     const int blocks = L.blocks;
     h->grid_blocks = blocks;
     // residual partials of the step kernel; tagged records of the persistent kernel
-    if ((rc = dalloc(h, &h->partials, (size_t)blocks * 5 + 10))) return fail(rc);
+    if ((rc = dalloc(h, &h->partials, step_partials_count(blocks)))) return fail(rc);
+    // the arrival counters behind the partials start at 0 and return to 0 every iteration
+    if (hipMemsetAsync(h->partials, 0, sizeof(double) * step_partials_count(blocks), h->stream) != hipSuccess)
+        return fail(set_err(h, OPF_EHIP, "memset"));
     if ((rc = dalloc(h, &h->pub, (size_t)h->LP * 4))) return fail(rc);
     if ((rc = dalloc(h, &h->records, (size_t)blocks * 10 * kDecisionLag))) return fail(rc);
     if ((rc = dalloc(h, &h->dec_iter, 1))) return fail(rc);
