@@ -152,6 +152,9 @@ template <typename T, int NT>
 __device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int* error, long long spin_limit) {
     __shared__ double rred[NT / 64][5];
     __shared__ int rstop;
+    // the reducer shares a compute unit with iteration workgroups: its waves
+    // issue first, so that the decisions keep pace with the iterations
+    __builtin_amdgcn_s_setprio(3);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     Ctrl* ctrl = v.ctrl;
     for (long long u = t0 + 1;; ++u) {
