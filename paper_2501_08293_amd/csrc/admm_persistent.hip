@@ -349,6 +349,10 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
         const u64* pubr = a.pub + (size_t)(t & 1) * LP * W;
         T acc = 0;
         if (live) {
+            // issue priority: low while waiting for the neighbours' terms, high
+            // once they are in, so that a workgroup that can compute goes ahead
+            // of the polling ones sharing its SIMDs
+            __builtin_amdgcn_s_setprio(0);
             u64 wd[kCopyRegs][W];
             unsigned pending = 0;       // copies whose word of iteration t has not arrived
 #pragma unroll
@@ -387,6 +391,7 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
                 }
                 acc += Tag<T>::unpack(we);
             }
+            __builtin_amdgcn_s_setprio(2);
         }
         if (threadIdx.x == 0) {
             while (dseen < tn - LAG && !bad && !errseen) {
