@@ -440,6 +440,9 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
             u64* pubw = a.pub + (size_t)(tn & 1) * LP * W + (size_t)d * W;
 #pragma unroll
             for (int h = 0; h < W; ++h) st_agent(pubw + h, wout[h]);
+            // the term the neighbours wait for is out; the residual tail yields
+            // to workgroups still on their way to publishing
+            __builtin_amdgcn_s_setprio(1);
             const double xd = (double)xg, zd = (double)z;
             s[0] = (xd - zd) * (xd - zd);
             s[1] = (zd - (double)zh[0]) * (zd - (double)zh[0]);
