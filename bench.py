@@ -424,7 +424,7 @@ def serve_leg(args, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "bench.py measures one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
