@@ -119,3 +119,35 @@ def test_redundant_consistent_rows_are_accepted_by_validation(inst):
         s.close()
     except binding.OpfError as e:
         assert e.code in (-5, -6), str(e)     # only a missing device may stop it
+
+
+STRUCTS = ["opf_problem", "opf_admm_options", "opf_warm", "opf_result", "opf_residuals", "opf_admm_info",
+           "opf_batch_result", "opf_server_options", "opf_served", "opf_server_stats"]
+
+
+def test_binding_layouts_match_the_c_compiler(tmp_path):
+    """Size and field offsets of every struct of the header, as the host C
+    compiler lays them out, equal the ctypes declarations of the binding."""
+    import shutil
+    import subprocess
+    binding, _ = _lib()
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "opf_admm.h"', "int main(void) {"]
+    for st in STRUCTS:
+        lines.append(f'    printf("{st} size %zu\\n", sizeof({st}));')
+        for field, _t in getattr(binding, st)._fields_:
+            lines.append(f'    printf("{st} {field} %zu\\n", offsetof({st}, {field}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st in STRUCTS:
+        cls = getattr(binding, st)
+        assert got[(st, "size")] == C.sizeof(cls), st
+        for field, _t in cls._fields_:
+            assert got[(st, field)] == getattr(cls, field).offset, (st, field)
