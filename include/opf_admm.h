@@ -217,10 +217,18 @@ int opf_admm_solve(opf_admm_handle* h, const opf_warm* warm, opf_result* r);
 int opf_admm_run_fixed(opf_admm_handle* h, const opf_warm* warm, int64_t iters, opf_result* r);
 
 /*
- * Residuals of the current state and, when hist != NULL, the per-iteration
- * history as rows (pres, dres, eps_prim, eps_dual): up to
- * min(hist_cap, options.history_cap, iterations) rows are written.  Returns the
- * number of rows written, or a negative error.
+ * Quantities of the termination test (Section III-C, eq. termination) at the
+ * last completed iteration of the handle:
+ *   pres     = sqrt(sum_s ||B_s x - x_s||^2),
+ *   dres     = rho sqrt(sum_s ||B_s^T (x_s^t - x_s^{t-1})||^2),
+ *   eps_prim = eps_rel max(sqrt(sum_s ||B_s x||^2), sqrt(sum_s ||x_s||^2)),
+ *   eps_dual = eps_rel sqrt(sum_s ||B_s^T lambda_s||^2),
+ * each sum accumulated in FP64 (B_s^T is an isometric injection, so these are
+ * the norms of the stacked slot vectors).  When hist != NULL (host, caller
+ * owned, 4 * hist_cap doubles) the per-iteration history is written as rows
+ * (pres, dres, eps_prim, eps_dual): up to min(hist_cap, options.history_cap,
+ * iterations) rows.  Returns the number of rows written, or a negative error
+ * (OPF_EINVAL for a NULL handle, OPF_EHIP).
  */
 int opf_admm_residuals(const opf_admm_handle* h, opf_residuals* out, double* hist, int hist_cap);
 
@@ -297,16 +305,23 @@ const char* opf_admm_batch_last_error(const opf_admm_batch* h);
  *
  * A request loop for many independent solves (feeders of different sizes and
  * switched topologies) arriving over time.  Submitted problems are set up on
- * host threads, admitted into a device arena while their memory footprint fits
- * (admission by HBM footprint), and iterated together: one launch of the
- * fused iteration kernel advances every resident solve by one iteration of
- * Algorithm 1, each with its own iteration count and termination test, so a
- * solve that arrives while others run joins the next launch (continuous
- * batching) and a finished one leaves it.  After a solve finishes its
- * (z, lambda) stay resident in HBM under its feeder family; a later request of
- * the same family starts from them component by component (warm start),
- * matching components by caller-supplied keys.  Precision is FP64; a solve
- * returns the same bits alone and in any mix.
+ * host threads and admitted into a device arena while their memory footprint
+ * fits (admission by HBM footprint).  The device works in rounds: one
+ * persistent launch per precision (the FP32 bulk phase of mixed-precision
+ * solves, then FP64: plain solves and polish phases) advances every resident
+ * solve by up to iters_per_poll iterations of Algorithm 1, each with its own
+ * iteration count and termination test (Section III-C).  Between rounds the
+ * host retires finished solves and admits waiting ones, so a solve that
+ * arrives while others run joins the next round (continuous batching).  A
+ * mixed-precision solve moves from the FP32 launch to the FP64 launch exactly
+ * where the single-instance solver hands over.
+ *
+ * After a solve finishes, its (z, lambda) stay resident in HBM under its
+ * feeder family; with warm_start on, a later request of the same family starts
+ * from them component by component, matching components by caller-supplied
+ * keys.  Bit identity: a cold-started solve returns the same bits alone, in any
+ * mix and as the single-instance solver with the same options; a warm-started
+ * solve depends on which state of its family is resident when it is admitted.
  */
 typedef struct opf_server opf_server;
 

@@ -248,10 +248,11 @@ class Result:
 
 
 def balance_factor(pres, dres, eps_prim, eps_dual, mu, tau):
-    """Residual balancing (the acceleration the paper points to in Section
-    III-D, after Wohlberg): compare the primal and dual residuals, each
-    relative to its tolerance, and scale rho up by tau when the primal one is
-    more than mu times larger, down by tau in the opposite case."""
+    """Residual balancing, the first acceleration Section III-D points to
+    (Wohlberg's relative form): the primal and dual residuals are compared
+    after each is divided by its tolerance of the termination test; the
+    penalty grows by tau when the primal one exceeds mu times the dual one,
+    shrinks by tau in the opposite case, else stays."""
     rp = pres / eps_prim if eps_prim > 0 else math.inf
     rd = dres / eps_dual if eps_dual > 0 else math.inf
     if rp > mu * rd:
@@ -267,23 +268,31 @@ def solve(P: Problem, rho: float = 100.0, eps_rel: float = 1e-3, max_iter: int =
     """Algorithm 1: global update, then local and dual updates, until the
     termination test holds (or max_iter / fixed_iters iterations).
 
-    balance = (every, mu, tau) enables residual balancing: after iteration t
-    with t % every == 0 the factor of balance_factor() applies to rho from
-    iteration t + 2 on (rho_{t+2} = rho_{t+1} * factor); rho_1 = rho_2 = rho.
-    The duals are kept unscaled, so a change of rho needs no rescaling, and
-    the projection factors do not depend on rho."""
+    balance = (every, mu, tau, lag, rho_min, rho_max) varies the penalty by
+    residual balancing: after iteration t with t % every == 0 the factor f of
+    balance_factor() on the residuals of t changes the penalty of iteration
+    t + lag on, rho_{t+lag} = min(max(rho_{t+lag-1} f, rho_min), rho_max); the
+    textbook rule is lag = 1 (the next iteration uses the new penalty).  Every
+    iteration t is one plain ADMM iteration with penalty rho_t: its global,
+    local and dual updates and its dual residual all use rho_t.  The duals are
+    kept unscaled, so a change of rho needs no rescaling of lambda, and the
+    projection factors do not depend on rho."""
     if z0 is None:
         z, lam = initial_point(P)
     else:
         z = np.array(z0, dtype=np.float64)
         lam = np.array(lam0, dtype=np.float64)
     hist = []
+    rhos = []
     x = np.minimum(np.maximum(np.zeros(P.n), P.lb), P.ub)
     t = 0
     converged = False
     r = (math.nan,) * 4
     limit = fixed_iters if fixed_iters is not None else max_iter
-    sched = {1: rho, 2: rho}          # rho used by iteration t
+    lag = int(balance[3]) if balance is not None else 1
+    if lag < 1:
+        raise ValueError("balance lag must be >= 1")
+    sched = {k: rho for k in range(1, lag + 1)}       # rho used by iteration k
     while t < limit:
         z_prev = z
         rt = sched[t + 1]
@@ -292,13 +301,15 @@ def solve(P: Problem, rho: float = 100.0, eps_rel: float = 1e-3, max_iter: int =
         lam = dual_update(P, x, z, lam, rt)
         t += 1
         r = residuals(P, x, z, z_prev, lam, rt, eps_rel)
-        f = 1.0
+        nxt = sched[t + lag - 1]
         if balance is not None and t % balance[0] == 0:
             f = balance_factor(r[0], r[1], r[2], r[3], balance[1], balance[2])
-        sched[t + 2] = sched[t + 1] * f
+            nxt = min(max(nxt * f, balance[4]), balance[5])
+        sched[t + lag] = nxt
         sched.pop(t, None)
         if record:
             hist.append(r)
+            rhos.append(rt)
         if progress is not None and t % progress == 0:
             print(f"oracle t={t} pres={r[0]:.3e}/{r[2]:.3e} dres={r[1]:.3e}/{r[3]:.3e}", flush=True)
         if fixed_iters is None and r[0] <= r[2] and r[1] <= r[3]:
@@ -308,4 +319,5 @@ def solve(P: Problem, rho: float = 100.0, eps_rel: float = 1e-3, max_iter: int =
                  pres=r[0], dres=r[1], eps_prim=r[2], eps_dual=r[3],
                  history=np.asarray(hist).reshape(-1, 4))
     res.rho_final = sched.get(t + 1, rho)
+    res.rho_history = np.asarray(rhos)          # rho used by iterations 1..t (when recorded)
     return res

@@ -120,21 +120,35 @@ class CentralLP:
                     co.append((("p", e, "ij", ps), mp[ph, ps]))
                     co.append((("q", e, "ij", ps), mq[ph, ps]))
                 eq(co, 0.0)
-        # power balance
+        # power balance (lines, loads and generators listed per bus first, in
+        # ascending order, so every row holds the same terms in the same order
+        # as a scan over all of them)
+        at_line = [[] for _ in range(f.n_bus)]
+        at_load = [[] for _ in range(f.n_bus)]
+        at_gen = [[] for _ in range(f.n_bus)]
+        for e, ln in enumerate(f.lines):
+            at_line[ln.parent].append(e)
+            if ln.child != ln.parent:
+                at_line[ln.child].append(e)
+        for l, ld in enumerate(f.loads):
+            at_load[ld.bus].append(l)
+        for k, g in enumerate(f.gens):
+            at_gen[g.bus].append(k)
         for i in range(f.n_bus):
             for ph in f.bus_phases[i]:
                 for a, gname, bname in (("p", "pg", "pb"), ("q", "qg", "qb")):
                     co = []
-                    for e, ln in enumerate(f.lines):
+                    for e in sorted(at_line[i]):
+                        ln = f.lines[e]
                         if ph in ln.phases and ln.parent == i:
                             co.append(((a, e, "ij", ph), 1.0))
                         if ph in ln.phases and ln.child == i:
                             co.append(((a, e, "ji", ph), 1.0))
-                    for l, ld in enumerate(f.loads):
-                        if ld.bus == i and ph in ld.phases:
+                    for l in at_load[i]:
+                        if ph in f.loads[l].phases:
                             co.append(((bname, l, ph), 1.0))
-                    for k, g in enumerate(f.gens):
-                        if g.bus == i and ph in g.phases:
+                    for k in at_gen[i]:
+                        if ph in f.gens[k].phases:
                             co.append(((gname, k, ph), -1.0))
                     eq(co, 0.0)
         # loads: voltage-dependent consumption, then wye / delta withdrawal

@@ -6,8 +6,11 @@ library has not been built; there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -115,6 +118,27 @@ class opf_server_stats(C.Structure):
 
 
 _lib = None
+
+# Handles still open when the interpreter exits are closed by an exit hook that
+# runs before the HIP runtime and any profiler attached to it shut down; a
+# handle's __del__ makes no HIP call while the interpreter is finalizing.
+_live = weakref.WeakSet()
+
+
+def close_all() -> None:
+    """Closes every open Solver, BatchSolver and Server of this process."""
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+atexit.register(close_all)
+
+
+def _finalizing() -> bool:
+    return sys.is_finalizing()
 
 
 def load(path: str = LIB_PATH):
@@ -320,6 +344,7 @@ class BatchSolver:
         o.check_every = check_every
         o.split_terms = split_terms
         self.h = opf_admm_setup_batch(_problem(keep, n), b_scen, o, stream, a_pos=a_pos, a_scen=a_scen)
+        _live.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -327,6 +352,8 @@ class BatchSolver:
             self.h = None
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -404,6 +431,7 @@ class Solver:
         self.options = o
         self.h = opf_admm_setup(p, o, stream)
         self._keep = None   # the library copied everything it needs
+        _live.add(self)
 
     @classmethod
     def from_arrays(cls, flat, **kw):
@@ -415,6 +443,8 @@ class Solver:
             self.h = None
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -513,6 +543,7 @@ class Server:
             raise OpfError(rc, lib.opf_server_last_error(None).decode())
         self.h = h
         self._pending = {}
+        _live.add(self)
 
     def submit(self, n, c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx, family=0, comp_keys=None) -> int:
         keep = _keep(c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx)
@@ -551,6 +582,8 @@ class Server:
             self.h = None
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:

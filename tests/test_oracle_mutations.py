@@ -1,11 +1,15 @@
 """Planted mistakes in the oracle (on the CPU only): each plausible slip in
 one step of Algorithm 1 must make at least one pin fail.  This checks that the
 pins constrain every step, not that the oracle is right."""
+import math
+
 import numpy as np
 import pytest
 
 from opfgen import build_instance, make_13bus
+from opfgen.random_lp import random_instance
 from oracle import admm
+from pin_helpers import termination_is_homogeneous, termination_matches_literal
 
 RHO = 100.0
 
@@ -137,3 +141,69 @@ def test_planted_factor_mistake_is_caught(base, monkeypatch):
     monkeypatch.setattr(admm, "local_factors", bad)
     P = admm.setup(inst)
     assert not _pins_hold(P, f)
+
+
+# ---- the termination quantities (Section III-C)
+
+def _mut_res_min(P, x, z, z_prev, lam, rho, eps_rel):
+    Bx = x[P.gidx]
+    pres = math.sqrt(float(np.sum((Bx - z) ** 2)))
+    dres = rho * math.sqrt(float(np.sum((z - z_prev) ** 2)))
+    eps_prim = eps_rel * min(math.sqrt(float(np.sum(Bx ** 2))), math.sqrt(float(np.sum(z ** 2))))
+    return pres, dres, eps_prim, eps_rel * math.sqrt(float(np.sum(lam ** 2)))
+
+
+def _mut_res_boyd_dual(P, x, z, z_prev, lam, rho, eps_rel):
+    # copies summed before the norm: ||B^T lambda|| instead of the stacked norm
+    pres, dres, eps_prim, _ = admm.__dict__["_orig_residuals"](P, x, z, z_prev, lam, rho, eps_rel)
+    return pres, dres, eps_prim, eps_rel * math.sqrt(float(np.sum(admm.B_T(P, lam) ** 2)))
+
+
+def _mut_res_prim_over_variables(P, x, z, z_prev, lam, rho, eps_rel):
+    # ||x|| over global variables instead of ||B x|| over slots
+    pres, dres, _, eps_dual = admm.__dict__["_orig_residuals"](P, x, z, z_prev, lam, rho, eps_rel)
+    eps_prim = eps_rel * max(math.sqrt(float(np.sum(x ** 2))), math.sqrt(float(np.sum(z ** 2))))
+    return pres, dres, eps_prim, eps_dual
+
+
+def _mut_res_dual_by_variables(P, x, z, z_prev, lam, rho, eps_rel):
+    # B^T applied to the change of the local copies (sums over copies)
+    pres, _, eps_prim, eps_dual = admm.__dict__["_orig_residuals"](P, x, z, z_prev, lam, rho, eps_rel)
+    return pres, rho * math.sqrt(float(np.sum(admm.B_T(P, z - z_prev) ** 2))), eps_prim, eps_dual
+
+
+def _mut_res_dres_no_rho(P, x, z, z_prev, lam, rho, eps_rel):
+    pres, dres, eps_prim, eps_dual = admm.__dict__["_orig_residuals"](P, x, z, z_prev, lam, rho, eps_rel)
+    return pres, dres / rho, eps_prim, eps_dual
+
+
+def _mut_res_squared_dual_tol(P, x, z, z_prev, lam, rho, eps_rel):
+    pres, dres, eps_prim, _ = admm.__dict__["_orig_residuals"](P, x, z, z_prev, lam, rho, eps_rel)
+    return pres, dres, eps_prim, eps_rel * float(np.sum(lam ** 2))
+
+
+def _mut_res_absolute_floor(P, x, z, z_prev, lam, rho, eps_rel):
+    pres, dres, eps_prim, eps_dual = admm.__dict__["_orig_residuals"](P, x, z, z_prev, lam, rho, eps_rel)
+    return pres, dres, eps_prim + eps_rel, eps_dual + eps_rel
+
+
+RES_MUTANTS = [_mut_res_min, _mut_res_boyd_dual, _mut_res_prim_over_variables, _mut_res_dual_by_variables,
+               _mut_res_dres_no_rho, _mut_res_squared_dual_tol, _mut_res_absolute_floor]
+
+
+def _termination_pins_hold():
+    """The termination pins: the printed sums with dense B_s (13-bus feeder and the
+    edge-case random LP) and homogeneity under an exact scaling of the LP."""
+    insts = (build_instance(make_13bus(0)), random_instance(0, n=160))
+    return all(termination_matches_literal(admm.setup(i)) and termination_is_homogeneous(i) for i in insts)
+
+
+def test_unmutated_termination_passes():
+    assert _termination_pins_hold()
+
+
+@pytest.mark.parametrize("mut", RES_MUTANTS, ids=[m.__name__ for m in RES_MUTANTS])
+def test_planted_termination_mistake_is_caught(monkeypatch, mut):
+    monkeypatch.setitem(admm.__dict__, "_orig_residuals", admm.residuals)
+    monkeypatch.setattr(admm, "residuals", mut)
+    assert not _termination_pins_hold()

@@ -10,6 +10,7 @@ from scipy.optimize import minimize_scalar
 from opfgen import build_instance, by_name, make_13bus
 from oracle import admm
 from oracle.central import CentralLP
+from pin_helpers import _trajectory, termination_is_homogeneous, termination_matches_literal
 
 RHO = 100.0
 
@@ -135,18 +136,6 @@ def test_initial_point_rule(P13):
 # --------------------------------------------------------------------------
 # invariants along the trajectory
 # --------------------------------------------------------------------------
-
-def _trajectory(P, iters):
-    z, lam = admm.initial_point(P)
-    out = []
-    for t in range(iters):
-        x = admm.global_update(P, z, lam, RHO)
-        zn = admm.local_update(P, x, lam, RHO)
-        lam = admm.dual_update(P, x, zn, lam, RHO)
-        out.append((x, zn, z, lam))
-        z = zn
-    return out
-
 
 def test_equality_blocks_hold_after_every_local_update(P13zip):
     """P1: ||A_s x_s - b_s||_inf <= 1e-12 max(1, ||b_s||_inf), original A_s."""
@@ -285,6 +274,49 @@ def test_termination_test_literal_reading():
     ok = (h[:, 0] <= h[:, 2]) & (h[:, 1] <= h[:, 3])
     assert ok[-1] and not ok[:-1].any()
     assert r.iterations == len(h)
+
+
+def test_termination_quantities_equal_the_printed_sums():
+    """Section III-C's pres, dres, eps_prim and eps_dual, evaluated literally with
+    dense B_s per component (B_s^T maps a component's vector into R^n), equal the
+    oracle's norms of the stacked slot vectors, at every one of the first
+    iterations on the 13-bus feeder and the edge-case random LP (a ten-copy
+    variable, equation-free components, infinite bounds)."""
+    from opfgen.random_lp import random_instance
+    for inst in (build_instance(make_13bus(0)), random_instance(0, n=160)):
+        assert termination_matches_literal(admm.setup(inst))
+
+
+@pytest.mark.parametrize("which", ["13bus", "random"])
+def test_termination_is_scale_invariant(which):
+    """Homogeneity: the residual history of the LP scaled by 8 is 8 times the
+    original one, and the stop iteration is the same (an absolute tolerance, a
+    squared or unsquared norm in the wrong place would break it)."""
+    from opfgen.random_lp import random_instance
+    inst = build_instance(make_13bus(0)) if which == "13bus" else random_instance(0, n=160)
+    assert termination_is_homogeneous(inst)
+
+
+def test_multiple_local_updates_collapse_to_a_scaled_dual_step():
+    """Several local updates per global update (Section III-D's second
+    acceleration): with x fixed, the closed-form local update followed by the
+    dual update, repeated k times, returns the same local copies as the first
+    update and the duals of one dual step of length k rho.  The reason: after a
+    dual update lambda_s lies in range(A_s^T), so (I - P_s) lambda_s = 0 and the
+    projection of x + lambda_s / rho equals that of x."""
+    P = admm.setup(build_instance(make_13bus(0)))
+    traj = _trajectory(P, 5)
+    x, z1, _, lam_prev = traj[-1]
+    lam0 = traj[-2][3]                    # lambda of iteration t-1: in range(A^T) already
+    for k in (2, 3, 5):
+        z = admm.local_update(P, x, lam0, RHO)
+        lam = admm.dual_update(P, x, z, lam0, RHO)
+        for _ in range(k - 1):
+            zk = admm.local_update(P, x, lam, RHO)
+            np.testing.assert_allclose(zk, z, rtol=0, atol=1e-12 * max(1.0, np.max(np.abs(z))))
+            lam = admm.dual_update(P, x, zk, lam, RHO)
+        np.testing.assert_allclose(lam, lam0 + k * RHO * (x[P.gidx] - z), rtol=0,
+                                   atol=1e-9 * max(1.0, np.max(np.abs(lam))))
 
 
 # --------------------------------------------------------------------------
