@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# residual balancing of the penalty measured beside the fixed-penalty headline
+BALANCE = dict(rho_every=10)
 BF16_DENSE_PEAK_TFLOPS = 2500.0
 METRIC = "8500-bus ADMM iters/s & time-to-1e-4 residual; served solves/s + p99 latency"
 KERNEL_SOURCES = ["paper_2501_08293_amd/csrc/admm_persistent.hip", "paper_2501_08293_amd/csrc/admm_kernels.h"]
@@ -65,6 +67,7 @@ def parse():
                     help="time this many iterations per step instead of solving to tolerance")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--skip-more", action="store_true", help="skip the other single-instance legs")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--batch-workload", default="2500bus")
     ap.add_argument("--batch-k", type=int, default=256)
@@ -83,25 +86,51 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(inst, eps, budget_s):
+def cpu_baseline(inst, eps, budget_s, workload):
     """The FP64 oracle timed on the host on a bounded sample of the same
-    workload: as many iterations of Algorithm 1 as fit in about budget_s."""
+    workload: as many iterations of Algorithm 1 as fit in about budget_s, in
+    one process and with the components split over worker processes (the
+    paper's CPU runs); time to tolerance extrapolated from the oracle's
+    stored iteration count at this tolerance."""
+    from threadpoolctl import threadpool_limits
     from oracle import admm
+    from oracle.parallel import solve_parallel
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(admm, solve_parallel, inst, eps, budget_s, workload)
+
+
+def _cpu_baseline(admm, solve_parallel, inst, eps, budget_s, workload):
     P = admm.setup(inst)
     t0 = time.perf_counter()
     admm.solve(P, rho=100.0, eps_rel=eps, fixed_iters=20, record=False)
     per = (time.perf_counter() - t0) / 20
-    iters = max(20, int(budget_s / max(per, 1e-6)))
+    iters = max(20, int(budget_s / 2 / max(per, 1e-6)))
     t0 = time.perf_counter()
     admm.solve(P, rho=100.0, eps_rel=eps, fixed_iters=iters, record=False)
-    dt = time.perf_counter() - t0
+    dt1 = time.perf_counter() - t0
+    rate1 = iters / dt1
     try:
         aff = len(os.sched_getaffinity(0))
     except Exception:
         aff = os.cpu_count()
-    return {"value": round(iters / dt, 2), "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} FP64 iterations of Algorithm 1 on the same {inst.name} instance from the default "
-                      f"start ({dt:.1f} s, NumPy on one thread; host affinity {aff} cores)"}
+    procs = max(1, min(16, aff) - 1)
+    itp = max(20, int(budget_s / 2 * rate1))
+    t0 = time.perf_counter()
+    solve_parallel(P, procs, rho=100.0, eps_rel=eps, fixed_iters=itp)
+    dtp = time.perf_counter() - t0
+    ratep = itp / dtp
+    ref = stored_reference(workload, eps)
+    out = {"value": round(ratep, 2), "unit": "iters/s", "cores": procs + 1, "kind": "oracle",
+           "sample": f"{itp} FP64 iterations of Algorithm 1 on the same {inst.name} instance from the default start "
+                     f"({dtp:.1f} s; components split over {procs} worker processes, global update and "
+                     f"termination test in the master; NumPy, one BLAS thread each; host affinity {aff} cores)",
+           "one_process": {"value": round(rate1, 2), "unit": "iters/s", "cores": 1,
+                           "sample": f"{iters} iterations in {dt1:.1f} s"}}
+    if "oracle_iterations" in ref:
+        out["time_to_tolerance_s_extrapolated"] = round(ref["oracle_iterations"] / ratep, 1)
+        out["one_process"]["time_to_tolerance_s_extrapolated"] = round(ref["oracle_iterations"] / rate1, 1)
+        out["oracle_iterations_to_tolerance"] = ref["oracle_iterations"]
+    return out
 
 
 def copy_calibration():
@@ -115,6 +144,35 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
+
+
+def stored_reference(workload, eps):
+    """Objective of the FP64 oracle's solve to eps and of the LP optimum
+    (HiGHS on the centralised LP), as stored under tests/golden (None when
+    not stored)."""
+    g = os.path.join(ROOT, "tests", "golden")
+    adm = os.path.join(g, f"admm_{workload}_s0_eps{eps:g}.json")
+    lp = os.path.join(g, f"lp_{workload}_s0.json")
+    out = {}
+    if os.path.exists(adm):
+        d = json.load(open(adm))
+        out["oracle_objective"] = d["objective"]
+        out["oracle_iterations"] = d["iterations"]
+        out["oracle_seconds_one_core"] = d.get("oracle_seconds")
+    if os.path.exists(lp):
+        out["lp_objective"] = json.load(open(lp))["objective"]
+    return out
+
+
+def accuracy(obj, ref):
+    """Relative objective error against the oracle's solve at the same
+    tolerance, and the gap to the LP optimum."""
+    acc = {}
+    if "oracle_objective" in ref:
+        acc["objective_rel_err_vs_oracle"] = abs(obj - ref["oracle_objective"]) / abs(ref["oracle_objective"])
+    if "lp_objective" in ref:
+        acc["lp_gap"] = (obj - ref["lp_objective"]) / abs(ref["lp_objective"])
+    return acc
 
 
 def traffic_from_profiles(workload, precision):
@@ -220,6 +278,7 @@ def single_instance(args, torch):
             "workgroups": info.grid_blocks,
             "factors_in_lds": info.factors_in_lds,
             "kernel_ms_per_solve": round(sum(r["kernel_ms"] for r in results) / args.steps, 3),
+            **accuracy(results[-1]["objective"], stored_reference(args.workload, args.eps)),
         },
         "roofline": {
             "bound": "hbm",
@@ -236,6 +295,64 @@ def single_instance(args, torch):
         },
     }
     return line, inst
+
+
+def solve_leg(workload, precision, eps, torch, steps=1, fixed=None, **kw):
+    """One workload solved `steps` times (or `fixed` iterations timed), with
+    the problem resident on the device: iterations, time, rate, accuracy and
+    the algorithmic-bytes rate of its iteration kernel."""
+    from opfgen import build_instance, by_name
+    from paper_2501_08293_amd import OPF_PREC_FP64, OPF_PREC_MIXED, Solver
+    inst = build_instance(by_name(workload, 0))
+    prec = OPF_PREC_MIXED if precision == "mixed" else OPF_PREC_FP64
+    stream = torch.cuda.Stream()
+    s = Solver(inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, *inst.flat(), rho=100.0, eps_rel=eps,
+               precision=prec, check_every=1024, stream=stream.cuda_stream, max_iter=3_000_000, **kw)
+    info = s.info()
+    x = torch.zeros(inst.n, dtype=torch.float64, device="cuda")
+    s.solve(x=x, fixed_iters=fixed)                      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [s.solve(x=x, fixed_iters=fixed) for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    s.close()
+    r = outs[-1]
+    it = int(r["iterations"])
+    elem = 4 if prec == OPF_PREC_MIXED else 8
+    bpi = algorithmic_bytes_per_iteration(info.sum_ns2, inst.L, inst.n, elem)
+    kms = r["kernel_ms_fp32"] if prec == OPF_PREC_MIXED else r["kernel_ms"]
+    kit = int(r["iterations_fp32"]) if prec == OPF_PREC_MIXED else it
+    gbs = bpi * kit / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    out = {"workload": f"{inst.name}: S={inst.S}, n={inst.n}, L={inst.L}", "precision": precision,
+           "eps_rel": eps, "status": int(r["status"]), "iterations": it, "iterations_fp32": int(r["iterations_fp32"]),
+           "ms": round(1e3 * wall, 3), "iters_per_s": round(it / wall, 1),
+           "kernel": {1: "step", 2: "persistent"}.get(info.kernel, "?"), "workgroups": info.grid_blocks,
+           "us_per_iteration": round(1e3 * kms / max(kit, 1), 3),
+           "algorithmic_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "objective": r["objective"]}
+    if kw:
+        out["options"] = kw
+        out["rho_final"] = r["rho_final"]
+    if fixed is None:
+        out.update(accuracy(r["objective"], stored_reference(workload, eps)))
+    return out
+
+
+def more_legs(args, torch):
+    """The other single-instance workloads of the measurement plan: the
+    headline feeder in FP64 (every step FP64), the 13- and 123-bus feeders
+    in both precisions, the 21000-bus (~30k component) feeder at a fixed
+    iteration count, and the headline with residual balancing of the penalty."""
+    legs = {}
+    legs["8500bus_fp64"] = solve_leg("8500bus", "fp64", args.eps, torch)
+    for w in ("13bus", "123bus"):
+        for p in ("fp64", "mixed"):
+            legs[f"{w}_{p}"] = solve_leg(w, p, args.eps, torch, steps=5)
+    legs["21000bus_mixed_fixed4096"] = solve_leg("21000bus", "mixed", args.eps, torch, fixed=4096)
+    legs["21000bus_fp64_fixed4096"] = solve_leg("21000bus", "fp64", args.eps, torch, fixed=4096)
+    legs["8500bus_mixed_balanced"] = solve_leg("8500bus", "mixed", args.eps, torch, **BALANCE)
+    return legs
 
 
 def batch_leg(args, torch):
@@ -262,14 +379,18 @@ def batch_leg(args, torch):
     mfma_flops = info.waves * chunks * 4 * 4 * 6 * (2 * 32 * 32 * 16) * T
     useful_flops = 2 * info.sum_ns2 * int(it.sum())
     tf = mfma_flops / wall / 1e12
-    # algorithmic bytes of one batch iteration (FP32 state, per scenario column):
-    # z and lambda read+write and bbar per slot (20 L), the consensus reads of
-    # z and lambda of every copy of each slot's variable (8 sum_i N_i^2), the x
-    # write (4 n); plus the three bf16 factor planes once (3 * 2 * 64 * 64 per wave)
+    # algorithmic bytes of one batch iteration: the shared FP64 factors once
+    # (8 sum n_s^2) and, per slot and scenario with FP32 state, lambda and z
+    # read and written, the x gather and bbar (24 B)
+    bytes_iter = 8 * info.sum_ns2 + K * inst.L * 24
+    gbs = bytes_iter * T / wall / 1e9
+    # what this design moves: z and lambda read+write and bbar per slot (20 L),
+    # the consensus reads of z and lambda of every copy of each slot's variable
+    # (8 sum_i N_i^2), the x write (4 n) per padded scenario column, and the
+    # three bf16 factor planes (3 * 2 * 64 * 64 per wave)
     cnt = np.bincount(np.concatenate([c.idx for c in inst.comps]), minlength=inst.n).astype(np.int64)
     per_col = 20 * inst.L + 8 * int((cnt * cnt).sum()) + 4 * inst.n
-    bytes_iter = 64 * chunks * per_col + 3 * 2 * 64 * 64 * info.waves
-    gbs = bytes_iter * T / wall / 1e9
+    design_bytes = 64 * chunks * per_col + 3 * 2 * 64 * 64 * info.waves
     return {
         "workload": f"{inst.name}: {K} load scenarios (lognormal(0, 0.3) per bus), shared A_s; eps_rel={args.eps:g}",
         "scenarios": K, "converged": int(out["converged"]), "status": int(out["status"]),
@@ -279,7 +400,9 @@ def batch_leg(args, torch):
         "scenario_iterations_per_s": round(float(it.sum()) / wall, 1),
         "us_per_batch_iteration": round(1e6 * wall / max(T, 1), 2),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_iteration": int(bytes_iter)},
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_iteration": int(bytes_iter),
+                     "design_bytes_per_iteration": int(design_bytes),
+                     "design_gbs": round(design_bytes * T / wall / 1e9, 1)},
         "mfma": {"issued_tflops": round(tf, 2), "peak_tflops_bf16_dense": BF16_DENSE_PEAK_TFLOPS,
                  "frac": round(tf / BF16_DENSE_PEAK_TFLOPS, 5),
                  "useful_fraction_of_issued": round(useful_flops * 6 / max(mfma_flops, 1), 4)},
@@ -441,6 +564,9 @@ def main():
     progress("single instance")
     line, inst = single_instance(args, torch)
     progress(f"single instance done: {line['ms_per_step']} ms per solve")
+    if not args.skip_more:
+        line["more"] = more_legs(args, torch)
+        progress("more single-instance legs done")
     if not args.skip_batch:
         line["batch"] = batch_leg(args, torch)
         progress(f"batch done: {line['batch']['time_to_all_ms']} ms")
@@ -448,7 +574,7 @@ def main():
         line["serving"] = serve_leg(args, torch)
         progress(f"serving done: {line['serving']['solves_per_s']} solves/s")
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(inst, args.eps, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(inst, args.eps, args.cpu_seconds, args.workload)
         progress("cpu baseline done")
     print(json.dumps(line), flush=True)
 

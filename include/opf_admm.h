@@ -129,8 +129,35 @@ typedef struct opf_admm_options {
                                (Section IV-B, closed_2; one workgroup per component) instead of
                                host threads; same results to rounding; components needing more
                                than 64 KiB of LDS make the set-up fail with OPF_EINVAL */
+    /* Residual balancing of the penalty, the first of the accelerations
+       Section III-D points to (Wohlberg's rule).  After every rho_every-th
+       iteration u the residuals of u are compared: with rho_mode
+       OPF_RHO_RELATIVE each is first divided by its tolerance of the
+       termination test (pres / eps_prim against dres / eps_dual), with
+       OPF_RHO_PLAIN they are compared as they are.  If the primal one exceeds
+       rho_mu times the dual one the penalty is multiplied by rho_tau, in the
+       opposite case divided by it, and then clipped to [rho_min, rho_max].
+       The new penalty takes effect OPF_RHO_LAG iterations after u (the
+       persistent kernel acts on decisions of earlier iterations; every
+       schedule applies the same lag, so all give the same iterates).  Every
+       iteration is one plain ADMM iteration with its own penalty: the duals
+       stay unscaled and the projection factors do not depend on rho, so
+       nothing is refactored.  rho_every = 0 keeps rho fixed (default).  With
+       rho_every > 0, zero fields take defaults: rho_mu 10, rho_tau 2,
+       rho_min rho / 10, rho_max 10 rho.  Each solve starts from rho; the
+       penalty reached is reported in opf_result.rho_final. */
+    int32_t rho_every;
+    int32_t rho_mode;       /* OPF_RHO_RELATIVE (0) or OPF_RHO_PLAIN (1) */
+    double  rho_mu;         /* >= 1 */
+    double  rho_tau;        /* > 1 */
+    double  rho_min;        /* 0 < rho_min <= rho */
+    double  rho_max;        /* rho <= rho_max */
     int32_t reserved[2];
 } opf_admm_options;
+
+#define OPF_RHO_RELATIVE 0
+#define OPF_RHO_PLAIN    1
+#define OPF_RHO_LAG      4   /* iterations between a balancing decision and its first use */
 
 /* Optional warm start: z0 and lambda0 in user slot order (length L). */
 typedef struct opf_warm {
@@ -158,6 +185,7 @@ typedef struct opf_result {
     double   kernel_ms;        /* device time of the iteration kernels (HIP events on the handle's stream) */
     double   kernel_ms_fp32;   /* MIXED: the part spent in the FP32 phase */
     int64_t  kernel_launches;  /* iteration-kernel launches (persistent: one per precision phase) */
+    double   rho_final;        /* penalty the next iteration would use (rho unless residual balancing) */
 } opf_result;
 
 typedef struct opf_residuals {

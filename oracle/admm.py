@@ -247,14 +247,18 @@ class Result:
     history: np.ndarray       # (iterations, 4): pres, dres, eps_prim, eps_dual
 
 
-def balance_factor(pres, dres, eps_prim, eps_dual, mu, tau):
+def balance_factor(pres, dres, eps_prim, eps_dual, mu, tau, relative=True):
     """Residual balancing, the first acceleration Section III-D points to
-    (Wohlberg's relative form): the primal and dual residuals are compared
-    after each is divided by its tolerance of the termination test; the
-    penalty grows by tau when the primal one exceeds mu times the dual one,
-    shrinks by tau in the opposite case, else stays."""
-    rp = pres / eps_prim if eps_prim > 0 else math.inf
-    rd = dres / eps_dual if eps_dual > 0 else math.inf
+    (Wohlberg): in the relative form the primal and dual residuals are
+    compared after each is divided by its tolerance of the termination test,
+    in the plain form as they are; the penalty grows by tau when the primal
+    one exceeds mu times the dual one, shrinks by tau in the opposite case,
+    else stays."""
+    if relative:
+        rp = pres / eps_prim if eps_prim > 0 else math.inf
+        rd = dres / eps_dual if eps_dual > 0 else math.inf
+    else:
+        rp, rd = pres, dres
     if rp > mu * rd:
         return tau
     if rd > mu * rp:
@@ -268,11 +272,12 @@ def solve(P: Problem, rho: float = 100.0, eps_rel: float = 1e-3, max_iter: int =
     """Algorithm 1: global update, then local and dual updates, until the
     termination test holds (or max_iter / fixed_iters iterations).
 
-    balance = (every, mu, tau, lag, rho_min, rho_max) varies the penalty by
-    residual balancing: after iteration t with t % every == 0 the factor f of
-    balance_factor() on the residuals of t changes the penalty of iteration
-    t + lag on, rho_{t+lag} = min(max(rho_{t+lag-1} f, rho_min), rho_max); the
-    textbook rule is lag = 1 (the next iteration uses the new penalty).  Every
+    balance = (every, mu, tau, lag, rho_min, rho_max[, relative]) varies the
+    penalty by residual balancing: after iteration t with t % every == 0 the
+    factor f of balance_factor() on the residuals of t changes the penalty of
+    iteration t + lag on, rho_{t+lag} = min(max(rho_{t+lag-1} f, rho_min),
+    rho_max); the textbook rule is lag = 1 (the next iteration uses the new
+    penalty); relative (default True) selects the form of balance_factor().  Every
     iteration t is one plain ADMM iteration with penalty rho_t: its global,
     local and dual updates and its dual residual all use rho_t.  The duals are
     kept unscaled, so a change of rho needs no rescaling of lambda, and the
@@ -303,7 +308,8 @@ def solve(P: Problem, rho: float = 100.0, eps_rel: float = 1e-3, max_iter: int =
         r = residuals(P, x, z, z_prev, lam, rt, eps_rel)
         nxt = sched[t + lag - 1]
         if balance is not None and t % balance[0] == 0:
-            f = balance_factor(r[0], r[1], r[2], r[3], balance[1], balance[2])
+            rel = bool(balance[6]) if len(balance) > 6 else True
+            f = balance_factor(r[0], r[1], r[2], r[3], balance[1], balance[2], rel)
             nxt = min(max(nxt * f, balance[4]), balance[5])
         sched[t + lag] = nxt
         sched.pop(t, None)

@@ -6,7 +6,8 @@ include/opf_admm.h; `binding` marshals arguments to it.  There is no CPU
 fallback: using the solver without the built library raises."""
 from . import binding
 from .binding import (OPF_KERNEL_AUTO, OPF_KERNEL_PERSISTENT, OPF_KERNEL_STEP, OPF_PREC_FP64,
-                      OPF_PREC_MIXED, BatchSolver, OpfError, Server, Solver)
+                      OPF_PREC_MIXED, OPF_RHO_LAG, OPF_RHO_PLAIN, OPF_RHO_RELATIVE, BatchSolver, OpfError, Server,
+                      Solver)
 
 __all__ = ["binding", "Solver", "BatchSolver", "Server", "OpfError", "OPF_PREC_FP64", "OPF_PREC_MIXED", "OPF_KERNEL_AUTO",
-           "OPF_KERNEL_STEP", "OPF_KERNEL_PERSISTENT"]
+           "OPF_KERNEL_STEP", "OPF_KERNEL_PERSISTENT", "OPF_RHO_RELATIVE", "OPF_RHO_PLAIN", "OPF_RHO_LAG"]

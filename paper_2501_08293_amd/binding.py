@@ -35,6 +35,10 @@ OPF_KERNEL_AUTO = 0
 OPF_KERNEL_STEP = 1
 OPF_KERNEL_PERSISTENT = 2
 
+OPF_RHO_RELATIVE = 0
+OPF_RHO_PLAIN = 1
+OPF_RHO_LAG = 4
+
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBOUNDS", -3: "EUNCOVERED",
                 -4: "EINFEASIBLE_COMPONENT", -5: "ENOMEM", -6: "EHIP", -7: "ENUMERIC", -8: "EHANG"}
 
@@ -58,7 +62,9 @@ class opf_admm_options(C.Structure):
                 ("precision", C.c_int32), ("polish", C.c_int32), ("check_every", C.c_int32),
                 ("kernel", C.c_int32), ("history_cap", C.c_int32), ("block_waves", C.c_int32),
                 ("spin_limit", C.c_int32), ("split_terms", C.c_int32), ("autotune", C.c_int32),
-                ("workgroup_order", C.c_int32), ("setup_on_device", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("workgroup_order", C.c_int32), ("setup_on_device", C.c_int32), ("rho_every", C.c_int32),
+                ("rho_mode", C.c_int32), ("rho_mu", C.c_double), ("rho_tau", C.c_double), ("rho_min", C.c_double),
+                ("rho_max", C.c_double), ("reserved", C.c_int32 * 2)]
 
 
 class opf_warm(C.Structure):
@@ -70,7 +76,8 @@ class opf_result(C.Structure):
                 ("status", C.c_int32), ("iterations", C.c_int64), ("iterations_fp32", C.c_int64),
                 ("objective", C.c_double), ("pres", C.c_double), ("dres", C.c_double),
                 ("eps_prim", C.c_double), ("eps_dual", C.c_double), ("solve_ms", C.c_double),
-                ("kernel_ms", C.c_double), ("kernel_ms_fp32", C.c_double), ("kernel_launches", C.c_int64)]
+                ("kernel_ms", C.c_double), ("kernel_ms_fp32", C.c_double), ("kernel_launches", C.c_int64),
+                ("rho_final", C.c_double)]
 
 
 class opf_residuals(C.Structure):
@@ -399,7 +406,8 @@ class Solver:
     def __init__(self, n, c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx, *, rho=100.0,
                  eps_rel=1e-3, max_iter=1_000_000, precision=OPF_PREC_FP64, polish=True, check_every=256,
                  kernel=OPF_KERNEL_AUTO, history_cap=0, block_waves=0, spin_limit=0, autotune=False,
-                 workgroup_order=0, setup_on_device=False, stream=0):
+                 workgroup_order=0, setup_on_device=False, rho_every=0, rho_mode=OPF_RHO_RELATIVE, rho_mu=0.0,
+                 rho_tau=0.0, rho_min=0.0, rho_max=0.0, stream=0):
         self._keep = dict(
             c=np.ascontiguousarray(c, np.float64), lb=np.ascontiguousarray(lb, np.float64),
             ub=np.ascontiguousarray(ub, np.float64), var_kind=np.ascontiguousarray(var_kind, np.uint8),
@@ -428,6 +436,12 @@ class Solver:
         o.autotune = int(bool(autotune))
         o.workgroup_order = workgroup_order
         o.setup_on_device = int(bool(setup_on_device))
+        o.rho_every = rho_every
+        o.rho_mode = rho_mode
+        o.rho_mu = rho_mu
+        o.rho_tau = rho_tau
+        o.rho_min = rho_min
+        o.rho_max = rho_max
         self.options = o
         self.h = opf_admm_setup(p, o, stream)
         self._keep = None   # the library copied everything it needs
@@ -500,7 +514,7 @@ class Solver:
         return dict(status=rc, x=x, z=z, lam=lam, iterations=r.iterations, iterations_fp32=r.iterations_fp32,
                     objective=r.objective, pres=r.pres, dres=r.dres, eps_prim=r.eps_prim, eps_dual=r.eps_dual,
                     solve_ms=r.solve_ms, kernel_ms=r.kernel_ms, kernel_ms_fp32=r.kernel_ms_fp32,
-                    kernel_launches=r.kernel_launches)
+                    kernel_launches=r.kernel_launches, rho_final=r.rho_final)
 
     def residuals(self, hist_cap=0):
         return opf_admm_residuals(self.h, hist_cap)

@@ -88,6 +88,44 @@ __device__ __forceinline__ T dual_step(T l, T rho, T x, T z) {
     return fmadd(rho, x - z, l);
 }
 
+// Residual balancing of the penalty (the acceleration of Section III-D, in
+// Wohlberg's form).  The penalty of iteration k lives in Ctrl::rho[k %
+// kRhoRing]; the decision taken on the residuals of iteration u writes the
+// penalty of iteration u + kRhoLag.  The persistent kernel learns the
+// decision of u only at the start of u + kDecisionLag, and the consensus
+// term it publishes at the end of that iteration already carries the next
+// iteration's 1/rho, hence one iteration more than the decision lag.
+constexpr int kRhoRing = 8;
+constexpr int kRhoLag = 4;
+
+struct RhoRule {
+    int every;             // 0: fixed penalty; else decide after every `every`-th iteration
+    int mode;              // 0: residuals relative to their tolerances; 1: plain residuals
+    double mu, tau, lo, hi;
+};
+
+// Factor of one balancing decision: tau when the primal residual exceeds mu
+// times the dual one, 1/tau in the opposite case, else 1.
+__host__ __device__ __forceinline__ double rho_factor(const RhoRule& r, double pres, double dres, double ep,
+                                                      double ed) {
+    double a = pres, b = dres;
+    if (r.mode == 0) {
+        a = ep > 0.0 ? pres / ep : __builtin_huge_val();
+        b = ed > 0.0 ? dres / ed : __builtin_huge_val();
+    }
+    if (a > r.mu * b) return r.tau;
+    if (b > r.mu * a) return 1.0 / r.tau;
+    return 1.0;
+}
+// Penalty of iteration u + kRhoLag from the one of u + kRhoLag - 1 and the
+// residuals of iteration u.
+__host__ __device__ __forceinline__ double rho_decide(const RhoRule& r, double prev, long long u, double pres,
+                                                      double dres, double ep, double ed) {
+    if (u % r.every != 0) return prev;
+    const double v = prev * rho_factor(r, pres, dres, ep, ed);
+    return v < r.lo ? r.lo : (v > r.hi ? r.hi : v);
+}
+
 // Control block in device memory; written by the last workgroup of each
 // iteration, read by the host between launches and by the next iteration.
 struct Ctrl {
@@ -99,6 +137,7 @@ struct Ctrl {
     unsigned int arrive;   // last-workgroup-done counter (returns to 0)
     double res[4];         // pres, dres, eps_prim, eps_dual of iteration `iter`
     double objective;      // c^T x (written by the output kernel)
+    double rho[kRhoRing];  // penalty of iteration k at rho[k % kRhoRing] (residual balancing only)
     long long pad[4];
 };
 
@@ -128,6 +167,7 @@ struct IterArgs {
     int waves;
     T rho, inv_rho;
     double rho_d, eps_rel;
+    RhoRule rule;               // rule.every == 0: rho fixed at rho_d
 };
 
 // Extra state of the persistent kernel (see admm_persistent.hip).

@@ -140,6 +140,7 @@ struct InstanceView {
                                // fit the launch's LDS), or with per-workgroup checks the column budget
     T rho, inv_rho;
     double rho_d, eps_rel;
+    RhoRule rule;              // rule.every == 0: fixed penalty; else the ring of ctrl->rho
     long long max_iter;
     long long chunk;           // the launch ends for this solve after this many iterations
 };
@@ -148,7 +149,7 @@ struct InstanceView {
 // decision ends the launch for the solve when the test holds, on a NaN/Inf,
 // at max_iter, or after `chunk` iterations of this launch (a pause: the solve
 // continues in the next launch from the state written at the pause).
-template <typename T, int NT>
+template <typename T, int NT, bool ADAPT>
 __device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int* error, long long spin_limit) {
     __shared__ double rred[NT / 64][5];
     __shared__ int rstop;
@@ -218,10 +219,18 @@ __device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int*
             for (int q = 0; q < NT / 64; ++q)
 #pragma unroll
                 for (int i = 0; i < 5; ++i) S[i] += rred[q][i];
+            const double rho_u = ADAPT ? ld_agent(&ctrl->rho[u % kRhoRing]) : v.rho_d;
             const double pres = sqrt(S[0]);
-            const double dres = v.rho_d * sqrt(S[1]);
+            const double dres = rho_u * sqrt(S[1]);
             const double ep = v.eps_rel * fmax(sqrt(S[2]), sqrt(S[3]));
             const double ed = v.eps_rel * sqrt(S[4]);
+            if (ADAPT) {
+                // penalty of iteration u + kRhoLag, visible before the decision of u is
+                const double nxt = rho_decide(v.rule, ld_agent(&ctrl->rho[(u + kRhoLag - 1) % kRhoRing]), u,
+                                              pres, dres, ep, ed);
+                st_agent(&ctrl->rho[(u + kRhoLag) % kRhoRing], nxt);
+                drain_memory();
+            }
             if (u - 1 < v.hist_cap) {
                 v.hist[(u - 1) * 4 + 0] = pres;
                 v.hist[(u - 1) * 4 + 1] = dres;
@@ -263,8 +272,10 @@ __device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int*
 // workgroups (b == G: its reducer).
 // PER_WG_LDS: each workgroup checks its own factor columns against the LDS
 // budget (serving, where one launch holds several solves); otherwise the
-// budget covers every workgroup of the launch.
-template <typename T, int WPB, bool PER_WG_LDS>
+// budget covers every workgroup of the launch.  ADAPT: the penalty follows
+// the residual-balancing ring of the control block (a separate instantiation,
+// so the fixed-penalty kernel keeps its registers).
+template <typename T, int WPB, bool PER_WG_LDS, bool ADAPT>
 __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int* error, long long spin_limit) {
     constexpr int NT = WPB * 64;
     constexpr int W = Tag<T>::W;
@@ -272,12 +283,13 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
     __shared__ T vsh[WPB][64];
     __shared__ double red[WPB][5];
     __shared__ int sh_flag;
+    __shared__ double sh_rho;
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     Ctrl* ctrl = a.ctrl;
     const long long t0 = ctrl->iter;
     if (b == G) {
-        reducer_loop<T, NT>(a, G, t0, error, spin_limit);
+        reducer_loop<T, NT, ADAPT>(a, G, t0, error, spin_limit);
         return;
     }
     const int w = b * WPB + wv;
@@ -322,7 +334,14 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
     }
     const int base = meta & 255;
     const bool owner = (meta >> 16) & 1;
-    const T inv_rho = a.inv_rho, rho = a.rho;
+    // penalty of the iteration being computed (residual balancing: from the
+    // ring, where the decision of tn - LAG put the penalty of tn + 1)
+    T inv_rho = a.inv_rho, rho = a.rho;
+    if (ADAPT) {
+        const double r0 = ld_agent(&ctrl->rho[(t0 + 1) % kRhoRing]);
+        rho = (T)r0;
+        inv_rho = (T)(1.0 / r0);
+    }
     // state of the last LAG iterations: index 0 = current iteration t
     T zh[LAG], lh[LAG], xh[LAG];
 #pragma unroll
@@ -401,8 +420,9 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
                 if (++spins > spin_limit) bad = 1;
             }
             int stop = 0;
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);   // dec_stop is read after dec_iter
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);   // dec_stop and the penalty are read after dec_iter
             if (!bad && !errseen && tn - LAG > t0) stop = ld_agent(a.dec_stop) == tn - LAG;
+            if (ADAPT && !bad && !errseen) sh_rho = ld_agent(&ctrl->rho[(tn + 1) % kRhoRing]);
             sh_flag = stop | (errseen ? 2 : 0);
         }
         if (__syncthreads_or(bad)) {
@@ -426,6 +446,13 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
         // The projection input is exchanged through this wavefront's own LDS
         // row only, and a wavefront's LDS operations complete in order, so a
         // wavefront barrier suffices here.
+        // 1/rho of iteration tn + 1, carried by the published consensus term
+        T inv_next = inv_rho;
+        double rho_next = 0.0;
+        if (ADAPT) {
+            rho_next = sh_rho;
+            inv_next = (T)(1.0 / rho_next);
+        }
         T xg = 0;
         if (live) xg = consensus_value(acc, cost, inv_rho, cn, lo, hi);
         vsh[wv][lane] = live ? projection_input(xg, lh[0], inv_rho) : (T)0;
@@ -436,7 +463,7 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
                                : project_row(Fg, vsh[wv], base, lane, wi.x, bb);
             const T ln = dual_step(lh[0], rho, xg, z);
             u64 wout[W];
-            Tag<T>::pack(copy_term(z, ln, inv_rho), (unsigned)tn, wout);
+            Tag<T>::pack(copy_term(z, ln, inv_next), (unsigned)tn, wout);
             u64* pubw = a.pub + (size_t)(tn & 1) * LP * W + (size_t)d * W;
 #pragma unroll
             for (int h = 0; h < W; ++h) st_agent(pubw + h, wout[h]);
@@ -477,6 +504,10 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
             st_agent(rw, two[0]);
             st_agent(rw + G, two[1]);
         }
+        if (ADAPT) {
+            rho = (T)rho_next;
+            inv_rho = inv_next;
+        }
         t = tn;
     }
 }
@@ -490,15 +521,15 @@ __device__ __forceinline__ InstanceView<T> view_of(const IterArgs<T>& a, const P
     v.pub = p.pub; v.records = p.records; v.dec_iter = p.dec_iter; v.dec_stop = p.dec_stop;
     v.ctrl = a.ctrl; v.hist = a.hist; v.hist_cap = a.hist_cap; v.waves = a.waves; v.check = p.check;
     v.lds_factors = p.lds_factors; v.rho = a.rho; v.inv_rho = a.inv_rho; v.rho_d = a.rho_d;
-    v.eps_rel = a.eps_rel; v.max_iter = p.max_iter; v.chunk = 0x3fffffffffffffffll;
+    v.eps_rel = a.eps_rel; v.rule = a.rule; v.max_iter = p.max_iter; v.chunk = 0x3fffffffffffffffll;
     return v;
 }
 
-template <typename T, int WPB>
+template <typename T, int WPB, bool ADAPT>
 __global__ __launch_bounds__(WPB * 64) void admm_persistent_kernel(IterArgs<T> a, PersistArgs p) {
     const InstanceView<T> v = view_of(a, p);
     const int b = logical_block((int)blockIdx.x, (int)gridDim.x, p.xcd_remap);
-    persistent_instance<T, WPB, false>(v, b, (int)gridDim.x - 1, p.error, p.spin_limit);
+    persistent_instance<T, WPB, false, ADAPT>(v, b, (int)gridDim.x - 1, p.error, p.spin_limit);
 }
 
 // Serving: the launch's workgroups are dealt to the resident solves by a work
@@ -538,7 +569,8 @@ __device__ __forceinline__ InstanceView<T> view_of(const InstDesc& D, const Serv
     v.pub = D.pub; v.records = D.records; v.dec_iter = D.dec; v.dec_stop = D.dec + 1;
     v.ctrl = D.ctrl; v.hist = nullptr; v.hist_cap = 0; v.waves = D.lanes / 64; v.check = D.ctrl->check;
     v.lds_factors = s.lds_cols; v.rho = (T)D.rho; v.inv_rho = (T)(1.0 / D.rho); v.rho_d = D.rho;
-    v.eps_rel = D.eps_rel; v.max_iter = D.ctrl->max_iter; v.chunk = s.chunk;
+    v.eps_rel = D.eps_rel; v.rule = RhoRule{0, 0, 0.0, 0.0, 0.0, 0.0};
+    v.max_iter = D.ctrl->max_iter; v.chunk = s.chunk;
     return v;
 }
 
@@ -552,7 +584,7 @@ __global__ __launch_bounds__(kServeWPB * 64) void admm_serve_kernel(const InstDe
     const InstDesc& D = descs[wk.x];
     if (D.ctrl->stop) return;               // finished solves stay resident until retired
     const InstanceView<T> v = view_of<T>(D, s);
-    persistent_instance<T, kServeWPB, true>(v, wk.y, D.blocks, s.error, s.spin_limit);
+    persistent_instance<T, kServeWPB, true, false>(v, wk.y, D.blocks, s.error, s.spin_limit);
 }
 
 // Before a serving launch: each work item prepares its own part of its solve
@@ -626,8 +658,9 @@ __global__ void persistent_prepare_kernel(IterArgs<T> a, PersistArgs p, int G) {
     if ((size_t)i < LP) {
         const T z = (t0 & 1) ? a.z1[i] : a.z0[i];
         const T l = (t0 & 1) ? a.l1[i] : a.l0[i];
+        const T inv = a.rule.every ? (T)(1.0 / a.ctrl->rho[(t0 + 1) % kRhoRing]) : a.inv_rho;
         u64 w[W];
-        Tag<T>::pack(copy_term(z, l, a.inv_rho), (unsigned)t0, w);
+        Tag<T>::pack(copy_term(z, l, inv), (unsigned)t0, w);
 #pragma unroll
         for (int h = 0; h < W; ++h) {
             p.pub[(size_t)i * W + h] = w[h];
@@ -642,6 +675,17 @@ __global__ void persistent_prepare_kernel(IterArgs<T> a, PersistArgs p, int G) {
     }
 }
 
+template <typename T, bool ADAPT>
+hipError_t launch_persistent_as(const IterArgs<T>& a, PersistArgs p, int wpb, int G, size_t lds, hipStream_t st) {
+    void* args[] = {(void*)&a, (void*)&p};
+    switch (wpb) {
+        case 1: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 1, ADAPT>, dim3(G + 1), dim3(64), args, lds, st);
+        case 2: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 2, ADAPT>, dim3(G + 1), dim3(128), args, lds, st);
+        case 8: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 8, ADAPT>, dim3(G + 1), dim3(512), args, lds, st);
+        default: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 4, ADAPT>, dim3(G + 1), dim3(256), args, lds, st);
+    }
+}
+
 template <typename T>
 hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G, hipStream_t st) {
     const size_t lds = p.lds_factors ? (size_t)p.lds_factor_cols * 64 * sizeof(T) : 0;
@@ -650,35 +694,36 @@ hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G
     hipLaunchKernelGGL((persistent_prepare_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, a, p, G);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    void* args[] = {(void*)&a, (void*)&p};
-    switch (wpb) {
-        case 1: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 1>, dim3(G + 1), dim3(64), args, lds, st);
-        case 2: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 2>, dim3(G + 1), dim3(128), args, lds, st);
-        case 8: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 8>, dim3(G + 1), dim3(512), args, lds, st);
-        default: return hipLaunchCooperativeKernel((const void*)admm_persistent_kernel<T, 4>, dim3(G + 1), dim3(256), args, lds, st);
-    }
+    return a.rule.every ? launch_persistent_as<T, true>(a, p, wpb, G, lds, st)
+                        : launch_persistent_as<T, false>(a, p, wpb, G, lds, st);
 }
 template hipError_t launch_persistent<double>(const IterArgs<double>&, PersistArgs, int, int, hipStream_t);
 template hipError_t launch_persistent<float>(const IterArgs<float>&, PersistArgs, int, int, hipStream_t);
 
-// Largest co-resident grid for the persistent kernel (0 on error); the grid
-// holds one workgroup more than the compute workgroups (the reducer).
-template <typename T>
-int persistent_capacity(int wpb, size_t lds_bytes) {
+template <typename T, bool ADAPT>
+int persistent_capacity_as(int wpb, size_t lds_bytes) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e;
     switch (wpb) {
-        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 1>, 64, lds_bytes); break;
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 2>, 128, lds_bytes); break;
-        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 8>, 512, lds_bytes); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 4>, 256, lds_bytes); break;
+        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 1, ADAPT>, 64, lds_bytes); break;
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 2, ADAPT>, 128, lds_bytes); break;
+        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 8, ADAPT>, 512, lds_bytes); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 4, ADAPT>, 256, lds_bytes); break;
     }
     if (e != hipSuccess) return 0;
     return per * cus;
 }
-template int persistent_capacity<double>(int, size_t);
-template int persistent_capacity<float>(int, size_t);
+
+// Largest co-resident grid for the persistent kernel (0 on error); the grid
+// holds one workgroup more than the compute workgroups (the reducer).
+// adapt = 1: the residual-balancing instantiation.
+template <typename T>
+int persistent_capacity(int wpb, size_t lds_bytes, int adapt) {
+    return adapt ? persistent_capacity_as<T, true>(wpb, lds_bytes) : persistent_capacity_as<T, false>(wpb, lds_bytes);
+}
+template int persistent_capacity<double>(int, size_t, int);
+template int persistent_capacity<float>(int, size_t, int);
 
 }  // namespace opf

@@ -36,7 +36,7 @@ __host__ __device__ constexpr size_t step_partials_doubles(size_t G) { return G 
 template <int NT>
 __device__ __forceinline__ void finish_iteration(const double (&s)[5], double* partials, Ctrl* ctrl,
                                                  double* hist, int hist_cap, long long t,
-                                                 double rho, double eps_rel) {
+                                                 double rho, double eps_rel, const RhoRule& rule) {
     unsigned* grp = reinterpret_cast<unsigned*>(partials + (size_t)gridDim.x * 5 + 16);
     __shared__ double red[NT / 64][5];
     __shared__ int is_last;
@@ -126,6 +126,9 @@ __device__ __forceinline__ void finish_iteration(const double (&s)[5], double* p
         ctrl->status = status;
         ctrl->stop = stop;
         ctrl->arrive = 0u;
+        if (rule.every)
+            ctrl->rho[(t + kRhoLag) % kRhoRing] =
+                rho_decide(rule, ctrl->rho[(t + kRhoLag - 1) % kRhoRing], t, pres, dres, ep, ed);
     }
 }
 
@@ -142,6 +145,14 @@ __global__ __launch_bounds__(WPB * 64) void admm_step_kernel(IterArgs<T> a) {
     T* zq = odd ? a.z1 : a.z0;
     T* lq = odd ? a.l1 : a.l0;
     T* xq = odd ? a.x1 : a.x0;
+    // penalty of this iteration (residual balancing: from the control block)
+    T rho = a.rho, inv_rho = a.inv_rho;
+    double rho_d = a.rho_d;
+    if (a.rule.every) {
+        rho_d = ctrl->rho[t % kRhoRing];
+        rho = (T)rho_d;
+        inv_rho = (T)(1.0 / rho_d);
+    }
 
     __shared__ T vsh[WPB][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -157,13 +168,13 @@ __global__ __launch_bounds__(WPB * 64) void admm_step_kernel(IterArgs<T> a) {
             T acc = 0;
             for (int k = 0; k < cn; ++k) {
                 const int e = a.clist[cs + k];
-                acc += copy_term(zp[e], lp[e], a.inv_rho);
+                acc += copy_term(zp[e], lp[e], inv_rho);
             }
-            xg = consensus_value(acc, a.cost[d], a.inv_rho, cn, a.lo[d], a.hi[d]);
+            xg = consensus_value(acc, a.cost[d], inv_rho, cn, a.lo[d], a.hi[d]);
             zold = zp[d];
             lold = lp[d];
         }
-        vsh[wv][lane] = (g >= 0) ? projection_input(xg, lold, a.inv_rho) : (T)0;
+        vsh[wv][lane] = (g >= 0) ? projection_input(xg, lold, inv_rho) : (T)0;
     }
     __syncthreads();
     double s[5] = {0, 0, 0, 0, 0};
@@ -172,7 +183,7 @@ __global__ __launch_bounds__(WPB * 64) void admm_step_kernel(IterArgs<T> a) {
         const T* Fw = a.F + (size_t)wi.y * 64;
         const int base = meta & 255;
         const T zn = project_row(Fw, vsh[wv], base, lane, wi.x, a.bbar[d]);
-        const T ln = dual_step(lold, a.rho, xg, zn);
+        const T ln = dual_step(lold, rho, xg, zn);
         zq[d] = zn;
         lq[d] = ln;
         if (meta & (1 << 16)) xq[g] = xg;
@@ -183,13 +194,13 @@ __global__ __launch_bounds__(WPB * 64) void admm_step_kernel(IterArgs<T> a) {
         s[3] = zd * zd;
         s[4] = (double)ln * (double)ln;
     }
-    finish_iteration<WPB * 64>(s, a.partials, ctrl, a.hist, a.hist_cap, t, a.rho_d, a.eps_rel);
+    finish_iteration<WPB * 64>(s, a.partials, ctrl, a.hist, a.hist_cap, t, rho_d, a.eps_rel, a.rule);
 }
 
 // Initial state: buffer 0 holds the start point (z0, lambda0) in device order.
 template <typename T>
 __global__ void init_state_kernel(const double* z0, const double* lam0, T* z, T* l, int LP,
-                                  Ctrl* ctrl, long long max_iter, int check) {
+                                  Ctrl* ctrl, long long max_iter, int check, double rho0) {
     const int d = blockIdx.x * blockDim.x + threadIdx.x;
     if (d < LP) {
         z[d] = (T)z0[d];
@@ -203,6 +214,7 @@ __global__ void init_state_kernel(const double* z0, const double* lam0, T* z, T*
         ctrl->check = check;
         ctrl->arrive = 0u;
         ctrl->res[0] = ctrl->res[1] = ctrl->res[2] = ctrl->res[3] = 0.0;
+        for (int k = 0; k < kRhoRing; ++k) ctrl->rho[k] = rho0;
     }
 }
 
@@ -291,15 +303,15 @@ template hipError_t launch_step<float>(const IterArgs<float>&, int, hipStream_t)
 
 template <typename T>
 hipError_t launch_init(const double* z0, const double* lam0, T* z, T* l, int LP, Ctrl* ctrl,
-                       long long max_iter, int check, hipStream_t st) {
+                       long long max_iter, int check, double rho0, hipStream_t st) {
     hipLaunchKernelGGL((init_state_kernel<T>), dim3((LP + 255) / 256), dim3(256), 0, st, z0, lam0, z, l,
-                       LP, ctrl, max_iter, check);
+                       LP, ctrl, max_iter, check, rho0);
     return hipGetLastError();
 }
 template hipError_t launch_init<double>(const double*, const double*, double*, double*, int, Ctrl*,
-                                        long long, int, hipStream_t);
+                                        long long, int, double, hipStream_t);
 template hipError_t launch_init<float>(const double*, const double*, float*, float*, int, Ctrl*,
-                                       long long, int, hipStream_t);
+                                       long long, int, double, hipStream_t);
 
 hipError_t launch_promote(const float* z32a, const float* z32b, const float* l32a, const float* l32b,
                           double* z64a, double* z64b, double* l64a, double* l64b, int LP, Ctrl* ctrl,

@@ -21,7 +21,7 @@ namespace opf {
 template <typename T> hipError_t launch_step(const IterArgs<T>& a, int wpb, hipStream_t st);
 template <typename T>
 hipError_t launch_init(const double* z0, const double* lam0, T* z, T* l, int LP, Ctrl* ctrl,
-                       long long max_iter, int check, hipStream_t st);
+                       long long max_iter, int check, double rho0, hipStream_t st);
 hipError_t launch_promote(const float* z32a, const float* z32b, const float* l32a, const float* l32b,
                           double* z64a, double* z64b, double* l64a, double* l64b, int LP, Ctrl* ctrl,
                           long long max_iter, int check, hipStream_t st);
@@ -29,7 +29,7 @@ hipError_t launch_rearm(Ctrl* ctrl, long long max_iter, int check, hipStream_t s
 size_t step_partials_count(int G);
 template <typename T>
 hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G, hipStream_t st);
-template <typename T> int persistent_capacity(int wpb, size_t lds_bytes);
+template <typename T> int persistent_capacity(int wpb, size_t lds_bytes, int adapt);
 template <typename T>
 hipError_t launch_output(const T* z0, const T* z1, const T* l0, const T* l1, const T* x0, const T* x1,
                          const int* user_slot, int LP, int n, const double* c, double* xo, double* zo,
@@ -37,6 +37,8 @@ hipError_t launch_output(const T* z0, const T* z1, const T* l0, const T* l1, con
 }  // namespace opf
 
 using namespace opf;
+
+static_assert(kRhoLag == OPF_RHO_LAG, "the balancing lag of the kernels is the one the header states");
 
 namespace {
 
@@ -61,6 +63,19 @@ struct PrecState {
     T* z[2] = {nullptr, nullptr};
     T* l[2] = {nullptr, nullptr};
     T* x[2] = {nullptr, nullptr};
+};
+
+// Scratch of the iteration kernels: the step kernel's residual partials and
+// arrival counters, the persistent kernel's published terms, residual
+// records, decision words and error flag.  A handle owns one set.
+struct Work {
+    double* partials = nullptr;
+    unsigned long long* pub = nullptr;     // published copy terms [2][LP][2] (tagged words)
+    unsigned long long* records = nullptr; // persistent residual records [lag][10][blocks]
+    long long* dec_iter = nullptr;
+    long long* dec_stop = nullptr;
+    int* dev_error = nullptr;
+    bool graphs = true;                    // step schedule: replay captured graphs (false: direct launches)
 };
 
 }  // namespace
@@ -109,11 +124,7 @@ struct opf_admm_handle {
     // persistent schedule
     int kernel = OPF_KERNEL_STEP;
     int capacity = 0;
-    unsigned long long* pub = nullptr;   // published copy terms [2][LP][2] (tagged words)
-    unsigned long long* records = nullptr;   // persistent residual records [lag][blocks][10]
-    long long* dec_iter = nullptr;
-    long long* dec_stop = nullptr;
-    int* dev_error = nullptr;
+    Work work;                     // the handle's own kernel scratch
     int xcd_remap = 1;
     int* error_host = nullptr;     // pinned
     double* devF = nullptr;        // factors from the device set-up (FP64, packed), else null
@@ -201,7 +212,7 @@ int make_prec(opf_admm_handle* h, PrecState<T>& s) {
 }
 
 template <typename T>
-IterArgs<T> iter_args(opf_admm_handle* h, PrecState<T>& s) {
+IterArgs<T> iter_args(opf_admm_handle* h, PrecState<T>& s, const Work& w) {
     IterArgs<T> a;
     a.F = s.F;
     a.winfo = h->winfo;
@@ -220,7 +231,7 @@ IterArgs<T> iter_args(opf_admm_handle* h, PrecState<T>& s) {
     a.l1 = s.l[1];
     a.x0 = s.x[0];
     a.x1 = s.x[1];
-    a.partials = h->partials;
+    a.partials = w.partials;
     a.ctrl = h->ctrl;
     a.hist = h->hist;
     a.hist_cap = h->opt.history_cap;
@@ -229,13 +240,15 @@ IterArgs<T> iter_args(opf_admm_handle* h, PrecState<T>& s) {
     a.inv_rho = (T)(1.0 / h->opt.rho);
     a.rho_d = h->opt.rho;
     a.eps_rel = h->opt.eps_rel;
+    a.rule = RhoRule{h->opt.rho_every, h->opt.rho_mode, h->opt.rho_mu, h->opt.rho_tau, h->opt.rho_min,
+                     h->opt.rho_max};
     return a;
 }
 
 // Captures `k` consecutive step launches into an executable graph.
 template <typename T>
 int capture_steps(opf_admm_handle* h, PrecState<T>& s, int k, hipGraphExec_t* out) {
-    IterArgs<T> a = iter_args(h, s);
+    IterArgs<T> a = iter_args(h, s, h->work);
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < k; ++i) {
@@ -254,9 +267,28 @@ int capture_steps(opf_admm_handle* h, PrecState<T>& s, int k, hipGraphExec_t* ou
 }
 
 // Runs step launches until the device stop flag is set.  Returns 0 or error.
+// Without graphs the `check_every` launches between host checks are issued
+// one by one (nothing is instantiated).
 template <typename T>
-int run_phase(opf_admm_handle* h, PrecState<T>& s, hipGraphExec_t* graph) {
+int run_phase(opf_admm_handle* h, PrecState<T>& s, hipGraphExec_t* graph, const Work& w) {
     const int k = std::max(1, h->opt.check_every);
+    if (!w.graphs) {
+        const IterArgs<T> a = iter_args(h, s, w);
+        const long long before = h->ctrl_host->iter;
+        for (;;) {
+            HIPCHK(hipEventRecord(h->ev0, h->stream));
+            for (int i = 0; i < k; ++i) HIPCHK(launch_step<T>(a, h->wpb, h->stream));
+            HIPCHK(hipEventRecord(h->ev1, h->stream));
+            HIPCHK(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+            h->kernel_ms += ms;
+            if (h->ctrl_host->stop) break;
+        }
+        h->kernel_launches += h->ctrl_host->iter - before;
+        return 0;
+    }
     if (!*graph || h->graph_k != k) {
         if (*graph) { (void)hipGraphExecDestroy(*graph); *graph = nullptr; }
         int rc = capture_steps(h, s, k, graph);
@@ -283,14 +315,14 @@ int run_phase(opf_admm_handle* h, PrecState<T>& s, hipGraphExec_t* graph) {
 }
 
 template <typename T>
-int run_phase_persistent(opf_admm_handle* h, PrecState<T>& s, long long max_iter, int check) {
-    IterArgs<T> a = iter_args(h, s);
+int run_phase_persistent(opf_admm_handle* h, PrecState<T>& s, long long max_iter, int check, const Work& w) {
+    IterArgs<T> a = iter_args(h, s, w);
     PersistArgs p;
-    p.pub = h->pub;
-    p.records = h->records;
-    p.dec_iter = h->dec_iter;
-    p.dec_stop = h->dec_stop;
-    p.error = h->dev_error;
+    p.pub = w.pub;
+    p.records = w.records;
+    p.dec_iter = w.dec_iter;
+    p.dec_stop = w.dec_stop;
+    p.error = w.dev_error;
     p.xcd_remap = h->xcd_remap;
     p.spin_limit = h->opt.spin_limit > 0 ? h->opt.spin_limit : 4000000LL;
     p.max_iter = max_iter;
@@ -301,7 +333,7 @@ int run_phase_persistent(opf_admm_handle* h, PrecState<T>& s, long long max_iter
     HIPCHK(launch_persistent<T>(a, p, h->wpb, h->lay.blocks, h->stream));
     HIPCHK(hipEventRecord(h->ev1, h->stream));
     HIPCHK(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipMemcpyAsync(h->error_host, h->dev_error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(h->error_host, w.dev_error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
@@ -315,9 +347,10 @@ int run_phase_persistent(opf_admm_handle* h, PrecState<T>& s, long long max_iter
 }
 
 template <typename T>
-int run_any(opf_admm_handle* h, PrecState<T>& s, hipGraphExec_t* graph, long long max_iter, int check) {
-    if (h->kernel == OPF_KERNEL_PERSISTENT) return run_phase_persistent<T>(h, s, max_iter, check);
-    return run_phase<T>(h, s, graph);
+int run_any(opf_admm_handle* h, PrecState<T>& s, hipGraphExec_t* graph, long long max_iter, int check,
+            const Work& w) {
+    if (h->kernel == OPF_KERNEL_PERSISTENT) return run_phase_persistent<T>(h, s, max_iter, check, w);
+    return run_phase<T>(h, s, graph, w);
 }
 
 template <typename T>
@@ -375,7 +408,7 @@ int prepare_start(opf_admm_handle* h, const opf_warm* warm, const double** z0, c
     return 0;
 }
 
-int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long long fixed_iters) {
+int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long long fixed_iters, const Work& w) {
     if (!h || !r || !r->x) return set_err(h, OPF_EINVAL, "null handle, result or x");
     auto t0 = std::chrono::steady_clock::now();
     if (h->user_stream != h->stream) HIPCHK(hipStreamSynchronize(h->user_stream));
@@ -398,8 +431,9 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
         // early when the residual ratio stops halving from window to window
         const bool watch = h->opt.polish && !fixed && h->opt.eps_rel < OPF_MIXED_STALL_BELOW;
         long long stop_at = watch ? std::min<long long>(OPF_MIXED_STALL_WINDOW, max_iter) : max_iter;
-        HIPCHK(launch_init<float>(z0, l0, h->s32.z[0], h->s32.l[0], h->LP, h->ctrl, stop_at, check, h->stream));
-        rc = run_any<float>(h, h->s32, &h->graph32, stop_at, check);
+        HIPCHK(launch_init<float>(z0, l0, h->s32.z[0], h->s32.l[0], h->LP, h->ctrl, stop_at, check, h->opt.rho,
+                                  h->stream));
+        rc = run_any<float>(h, h->s32, &h->graph32, stop_at, check, w);
         if (rc) return rc;
         double q_prev = HUGE_VAL;
         while (watch && h->ctrl_host->status == OPF_NOT_CONVERGED && h->ctrl_host->iter < max_iter) {
@@ -409,7 +443,7 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
             q_prev = q;
             stop_at = std::min<long long>(c.iter + OPF_MIXED_STALL_WINDOW, max_iter);
             HIPCHK(launch_rearm(h->ctrl, stop_at, check, h->stream));
-            rc = run_any<float>(h, h->s32, &h->graph32, stop_at, check);
+            rc = run_any<float>(h, h->s32, &h->graph32, stop_at, check, w);
             if (rc) return rc;
         }
         it32 = h->ctrl_host->iter;
@@ -419,15 +453,16 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
         if (polish) {
             HIPCHK(launch_promote(h->s32.z[0], h->s32.z[1], h->s32.l[0], h->s32.l[1], h->s64.z[0], h->s64.z[1],
                                   h->s64.l[0], h->s64.l[1], h->LP, h->ctrl, it32 + h->opt.max_iter, 1, h->stream));
-            rc = run_any<double>(h, h->s64, &h->graph64, it32 + h->opt.max_iter, 1);
+            rc = run_any<double>(h, h->s64, &h->graph64, it32 + h->opt.max_iter, 1, w);
             if (rc) return rc;
             status = h->ctrl_host->status;
         } else {
             final64 = false;
         }
     } else {
-        HIPCHK(launch_init<double>(z0, l0, h->s64.z[0], h->s64.l[0], h->LP, h->ctrl, max_iter, check, h->stream));
-        rc = run_any<double>(h, h->s64, &h->graph64, max_iter, check);
+        HIPCHK(launch_init<double>(z0, l0, h->s64.z[0], h->s64.l[0], h->LP, h->ctrl, max_iter, check, h->opt.rho,
+                                   h->stream));
+        rc = run_any<double>(h, h->s64, &h->graph64, max_iter, check, w);
         if (rc) return rc;
         status = h->ctrl_host->status;
     }
@@ -444,6 +479,7 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
     r->status = status;
     r->kernel_ms = h->kernel_ms;
     r->kernel_launches = h->kernel_launches;
+    r->rho_final = h->opt.rho_every ? c.rho[(c.iter + 1) % kRhoRing] : h->opt.rho;
     h->last_iter = c.iter;
     h->last_prec = final64 ? OPF_PREC_FP64 : OPF_PREC_MIXED;
     r->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -568,6 +604,19 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     if (opt.precision != OPF_PREC_FP64 && opt.precision != OPF_PREC_MIXED)
         return set_err(nullptr, OPF_EINVAL, "unknown precision");
     if (opt.history_cap < 0) return set_err(nullptr, OPF_EINVAL, "history_cap must be >= 0");
+    if (opt.rho_every < 0) return set_err(nullptr, OPF_EINVAL, "rho_every must be >= 0");
+    if (opt.rho_every > 0) {
+        if (opt.rho_mu == 0.0) opt.rho_mu = 10.0;
+        if (opt.rho_tau == 0.0) opt.rho_tau = 2.0;
+        if (opt.rho_min == 0.0) opt.rho_min = opt.rho / 10.0;
+        if (opt.rho_max == 0.0) opt.rho_max = opt.rho * 10.0;
+        if (opt.rho_mode != OPF_RHO_RELATIVE && opt.rho_mode != OPF_RHO_PLAIN)
+            return set_err(nullptr, OPF_EINVAL, "unknown rho_mode");
+        if (!(opt.rho_mu >= 1.0) || !(opt.rho_tau > 1.0) || !std::isfinite(opt.rho_mu) || !std::isfinite(opt.rho_tau))
+            return set_err(nullptr, OPF_EINVAL, "residual balancing needs rho_mu >= 1 and rho_tau > 1");
+        if (!(opt.rho_min > 0.0) || !(opt.rho_min <= opt.rho) || !(opt.rho <= opt.rho_max) || !std::isfinite(opt.rho_max))
+            return set_err(nullptr, OPF_EINVAL, "residual balancing needs 0 < rho_min <= rho <= rho_max < inf");
+    }
     if (opt.check_every < 1) opt.check_every = 256;
     auto t0 = std::chrono::steady_clock::now();
     ProblemView v;
@@ -627,15 +676,16 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     const int blocks = L.blocks;
     h->grid_blocks = blocks;
     // residual partials of the step kernel; tagged records of the persistent kernel
-    if ((rc = dalloc(h, &h->partials, step_partials_count(blocks)))) return fail(rc);
+    Work& w = h->work;
+    if ((rc = dalloc(h, &w.partials, step_partials_count(blocks)))) return fail(rc);
     // the arrival counters behind the partials start at 0 and return to 0 every iteration
-    if (hipMemsetAsync(h->partials, 0, sizeof(double) * step_partials_count(blocks), h->stream) != hipSuccess)
+    if (hipMemsetAsync(w.partials, 0, sizeof(double) * step_partials_count(blocks), h->stream) != hipSuccess)
         return fail(set_err(h, OPF_EHIP, "memset"));
-    if ((rc = dalloc(h, &h->pub, (size_t)h->LP * 4))) return fail(rc);
-    if ((rc = dalloc(h, &h->records, (size_t)blocks * 10 * kDecisionLag))) return fail(rc);
-    if ((rc = dalloc(h, &h->dec_iter, 1))) return fail(rc);
-    if ((rc = dalloc(h, &h->dec_stop, 1))) return fail(rc);
-    if ((rc = dalloc(h, &h->dev_error, 1))) return fail(rc);
+    if ((rc = dalloc(h, &w.pub, (size_t)h->LP * 4))) return fail(rc);
+    if ((rc = dalloc(h, &w.records, (size_t)blocks * 10 * kDecisionLag))) return fail(rc);
+    if ((rc = dalloc(h, &w.dec_iter, 1))) return fail(rc);
+    if ((rc = dalloc(h, &w.dec_stop, 1))) return fail(rc);
+    if ((rc = dalloc(h, &w.dev_error, 1))) return fail(rc);
     if (hipHostMalloc((void**)&h->error_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return fail(set_err(h, OPF_ENOMEM, "hipHostMalloc failed"));
     *h->error_host = 0;
@@ -648,12 +698,13 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     }
     const size_t lds_limit = 64 * 1024;
     const size_t l64 = (size_t)h->lds_cols * 64 * 8, l32 = (size_t)h->lds_cols * 64 * 4;
-    const int cap64_lds = l64 <= lds_limit ? persistent_capacity<double>(h->wpb, l64) : 0;
-    const int cap32_lds = l32 <= lds_limit ? persistent_capacity<float>(h->wpb, l32) : 0;
+    const int ad = opt.rho_every > 0;
+    const int cap64_lds = l64 <= lds_limit ? persistent_capacity<double>(h->wpb, l64, ad) : 0;
+    const int cap32_lds = l32 <= lds_limit ? persistent_capacity<float>(h->wpb, l32, ad) : 0;
     h->lds64 = cap64_lds >= blocks + 1;
     h->lds32 = cap32_lds >= blocks + 1;
-    const int cap64 = h->lds64 ? cap64_lds : persistent_capacity<double>(h->wpb, 0);
-    const int cap32 = h->lds32 ? cap32_lds : persistent_capacity<float>(h->wpb, 0);
+    const int cap64 = h->lds64 ? cap64_lds : persistent_capacity<double>(h->wpb, 0, ad);
+    const int cap32 = h->lds32 ? cap32_lds : persistent_capacity<float>(h->wpb, 0, ad);
     h->capacity = opt.precision == OPF_PREC_MIXED ? std::min(cap32, cap64) : cap64;
     if (opt.kernel == OPF_KERNEL_PERSISTENT && h->capacity < blocks + 1)
         return fail(set_err(h, OPF_EINVAL, "persistent kernel needs " + std::to_string(blocks + 1) +
@@ -677,12 +728,14 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
 }
 
 int opf_admm_solve(opf_admm_handle* h, const opf_warm* warm, opf_result* r) {
-    return solve_impl(h, warm, r, 0);
+    if (!h) return set_err(nullptr, OPF_EINVAL, "null handle");
+    return solve_impl(h, warm, r, 0, h->work);
 }
 
 int opf_admm_run_fixed(opf_admm_handle* h, const opf_warm* warm, int64_t iters, opf_result* r) {
+    if (!h) return set_err(nullptr, OPF_EINVAL, "null handle");
     if (iters < 1) return set_err(h, OPF_EINVAL, "iters must be >= 1");
-    return solve_impl(h, warm, r, iters);
+    return solve_impl(h, warm, r, iters, h->work);
 }
 
 int opf_admm_residuals(const opf_admm_handle* hc, opf_residuals* out, double* hist, int hist_cap) {

@@ -5,6 +5,7 @@ touches the HIP library.
     python tests/golden/make_golden.py 13bus 123bus     # seconds
     python tests/golden/make_golden.py 8500bus:1e-4     # tens of minutes
     python tests/golden/make_golden.py lp:8500bus       # LP optimum by HiGHS
+    python tests/golden/make_golden.py 2500bus@scen3:1e-4   # scenario 3 of the batch benchmark
 """
 import json
 import os
@@ -16,16 +17,23 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from opfgen import by_name, build_instance  # noqa: E402
+from opfgen import build_instance, by_name, scenario_load_factors, scenario_rhs, with_rhs  # noqa: E402
 from oracle import admm  # noqa: E402
 from oracle.central import CentralLP  # noqa: E402
 
 RHO = 100.0
 
 
-def golden(name, seed=0, eps_rel=1e-4, n_sample=256):
+def golden(name, seed=0, eps_rel=1e-4, n_sample=256, scenario=None):
     f = by_name(name, seed)
     inst = build_instance(f)
+    tag = name
+    if scenario is not None:
+        # scenario k of the benchmark's batch: every bus's load scaled by the
+        # k-th draw of lognormal(0, 0.3) (stream seed 1000, 256 scenarios)
+        k = int(scenario)
+        inst = with_rhs(inst, scenario_rhs(inst, scenario_load_factors(f, 256, seed=1000))[k])
+        tag = f"{name}-scen{k}"
     P = admm.setup(inst)
     t0 = time.time()
     r = admm.solve(P, rho=RHO, eps_rel=eps_rel, max_iter=2_000_000, record=True, progress=5000)
@@ -37,7 +45,7 @@ def golden(name, seed=0, eps_rel=1e-4, n_sample=256):
     hist = r.history
     m = hist[:, 0] ** 2 + (hist[:, 1] / RHO) ** 2
     out = dict(
-        workload=name, seed=seed, rho=RHO, eps_rel=eps_rel, stats=inst.stats(),
+        workload=tag, seed=seed, rho=RHO, eps_rel=eps_rel, stats=inst.stats(),
         iterations=int(r.iterations), converged=bool(r.converged), objective=r.objective,
         pres=r.pres, dres=r.dres, eps_prim=r.eps_prim, eps_dual=r.eps_dual,
         w_index=[int(i) for i in samp], w_value=[float(r.x[i]) for i in samp],
@@ -50,7 +58,7 @@ def golden(name, seed=0, eps_rel=1e-4, n_sample=256):
         oracle_seconds=dt,
         source="oracle/admm.py solve() on opfgen.by_name(workload, seed); written by tests/golden/make_golden.py",
     )
-    path = os.path.join(HERE, f"admm_{name}_s{seed}_eps{eps_rel:g}.json")
+    path = os.path.join(HERE, f"admm_{tag}_s{seed}_eps{eps_rel:g}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(f"wrote {path}: {r.iterations} iterations, objective {r.objective:.12g}, {dt:.1f}s", flush=True)
@@ -92,4 +100,7 @@ if __name__ == "__main__":
         if ":" in nm:
             nm, e = nm.split(":")
             eps = float(e)
-        golden(nm, eps_rel=eps)
+        scen = None
+        if "@scen" in nm:
+            nm, scen = nm.split("@scen")
+        golden(nm, eps_rel=eps, scenario=scen)

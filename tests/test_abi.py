@@ -31,9 +31,10 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header_layout():
     binding, _ = _lib()
     assert C.sizeof(binding.opf_problem) == 88
-    assert C.sizeof(binding.opf_admm_options) == 8 + 8 + 8 + 6 * 4 + 7 * 4 + 4
+    # rho, eps_rel, max_iter; thirteen int32 fields and 4 bytes of padding; four doubles; two reserved int32
+    assert C.sizeof(binding.opf_admm_options) == 8 + 8 + 8 + 13 * 4 + 4 + 4 * 8 + 2 * 4
     assert C.sizeof(binding.opf_batch_result) == 8 + 4 + 4 + 7 * 8 + 8 + 4 + 4 + 8
-    assert C.sizeof(binding.opf_result) == 3 * 8 + 4 + 4 + 8 + 8 + 6 * 8 + 8 + 8 + 8
+    assert C.sizeof(binding.opf_result) == 3 * 8 + 4 + 4 + 8 + 8 + 6 * 8 + 8 + 8 + 8 + 8
 
 
 def test_default_options_are_the_papers():
@@ -56,6 +57,25 @@ def _setup_expect(code, n, c, lb, ub, kind, cm, cn, A, b, idx):
 @pytest.fixture(scope="module")
 def inst():
     return build_instance(make_13bus(0))
+
+
+@pytest.mark.parametrize("kw", [dict(rho_every=-1), dict(rho_every=5, rho_tau=1.0), dict(rho_every=5, rho_mu=0.5),
+                                dict(rho_every=5, rho_min=200.0), dict(rho_every=5, rho_max=50.0),
+                                dict(rho_every=5, rho_mode=7)])
+def test_rejects_invalid_balancing_options(inst, kw):
+    binding, _ = _lib()
+    with pytest.raises(binding.OpfError) as e:
+        binding.Solver(inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, *inst.flat(), rho=100.0, **kw)
+    assert e.value.code == binding.OPF_EINVAL, str(e.value)
+
+
+def test_server_rejects_balancing():
+    binding, lib = _lib()
+    o = binding.opf_server_default_options()
+    o.admm.rho_every = 10
+    h = C.c_void_p()
+    assert lib.opf_server_create(C.byref(o), None, C.byref(h)) == binding.OPF_EINVAL
+    assert not h.value
 
 
 def test_rejects_lb_above_ub(inst):

@@ -150,3 +150,56 @@ def test_zip_scenarios_on_constant_power_equal_shared_path():
     o2 = s2.solve()
     s2.close()
     assert np.array_equal(o1["x"], o2["x"]) and np.array_equal(o1["iterations"], o2["iterations"])
+
+
+@pytest.fixture(scope="module")
+def case2500():
+    """The benchmark's batch: 2500-bus feeder, 256 load scenarios (stream seed
+    1000), four 64-scenario chunks on the MFMA tiles."""
+    f = by_name("2500bus", 0)
+    inst = build_instance(f)
+    return inst, scenario_rhs(inst, scenario_load_factors(f, 256, seed=1000))
+
+
+def test_full_size_batch_early_iterates_match_oracle(case2500):
+    """At the benchmark's size and launch configuration (K = 256): sampled
+    scenarios from every 64-scenario chunk after 20 iterations against the
+    oracle's 20th iterate of each (1e-5 relative)."""
+    inst, B = case2500
+    _say("[gpu] batch 2500bus K=256 t=20, scenarios 0, 70, 141, 255 vs oracle")
+    s = _batch(inst, B, rho=RHO, eps_rel=1e-12, max_iter=20, check_every=4)
+    out = s.solve()
+    s.close()
+    assert np.all(out["iterations"] == 20)
+    for k in (0, 70, 141, 255):
+        P = admm.setup(with_rhs(inst, B[k]))
+        ref = admm.solve(P, rho=RHO, eps_rel=1e-12, fixed_iters=20, record=False)
+        err = np.max(np.abs(out["x"][k] - ref.x)) / max(1.0, np.max(np.abs(ref.x)))
+        assert err < 1e-5, (k, err)
+
+
+def test_full_size_batch_solve_matches_golden_scenario(case2500):
+    """The benchmark's batch solved to eps_rel = 1e-4: scenario 3 against the
+    oracle's solve of that scenario to the same tolerance (stored golden):
+    objective and sampled voltages within 1e-4 relative, stop iteration
+    within 2 %; every scenario converges."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "admm_2500bus-scen3_s0_eps0.0001.json")
+    if not os.path.exists(path):
+        pytest.skip("golden of batch scenario 3 not written yet")
+    g = json.load(open(path))
+    inst, B = case2500
+    _say("[gpu] batch 2500bus K=256 eps=1e-4 (benchmark configuration), scenario 3 vs golden")
+    s = _batch(inst, B, rho=RHO, eps_rel=1e-4, check_every=256)
+    out = s.solve()
+    s.close()
+    assert out["status"] == 0 and out["converged"] == 256
+    k = 3
+    _say(f"  scenario 3: iterations {out['iterations'][k]} (oracle {g['iterations']}), objective "
+         f"{out['objective'][k]:.10g} (oracle {g['objective']:.10g})")
+    assert abs(out["objective"][k] - g["objective"]) <= 1e-4 * abs(g["objective"])
+    w = out["x"][k][g["w_index"]]
+    ref_w = np.array(g["w_value"])
+    assert np.max(np.abs(w - ref_w) / np.abs(ref_w)) <= 1e-4
+    assert abs(int(out["iterations"][k]) - g["iterations"]) <= 0.02 * g["iterations"]

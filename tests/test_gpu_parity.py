@@ -303,6 +303,53 @@ def test_full_size_8500bus_mixed_benchmark_configuration():
     _say(f"  iterations {out['iterations']} ({out['iterations_fp32']} FP32), golden {g['iterations']}")
 
 
+def test_headline_8500bus_mixed_eps1e4_matches_oracle():
+    """The benchmark's headline configuration exactly (8500-bus, eps_rel =
+    1e-4, mixed precision: FP32 persistent bulk with FP64 residual sums, then
+    FP64 polish; check_every 1024, default schedule) against the FP64
+    oracle's solve to the same tolerance: objective and sampled voltages
+    within the mixed-precision bar of 1e-4 relative, and the stop iteration
+    within 1 % of the oracle's (FP32 rounding moves the iteration at which
+    the test first holds)."""
+    from paper_2501_08293_amd import OPF_PREC_MIXED
+    _say("[gpu] 8500bus mixed eps=1e-4 (headline configuration) vs golden")
+    g = _golden("8500bus", 1e-4)
+    s = _solver(_inst("8500bus"), rho=RHO, eps_rel=1e-4, precision=OPF_PREC_MIXED, check_every=1024)
+    out = s.solve()
+    s.close()
+    _say(f"  iterations {out['iterations']} ({out['iterations_fp32']} FP32), golden {g['iterations']}; "
+         f"objective {out['objective']:.10g}, golden {g['objective']:.10g}")
+    assert out["status"] == 0
+    assert abs(out["iterations"] - g["iterations"]) <= 0.01 * g["iterations"]
+    assert abs(out["objective"] - g["objective"]) <= 1e-4 * abs(g["objective"])
+    w = out["x"][g["w_index"]]
+    ref_w = np.array(g["w_value"])
+    assert np.max(np.abs(w - ref_w) / np.abs(ref_w)) <= 1e-4
+    xs = out["x"][g["x_index"]]
+    ref_x = np.array(g["x_value"])
+    assert np.max(np.abs(xs - ref_x)) <= 1e-4 * max(1.0, float(np.max(np.abs(ref_x))))
+
+
+def test_headline_8500bus_fp64_eps1e4_matches_oracle():
+    """The headline workload in FP64 (every step FP64, persistent schedule)
+    against the oracle's solve to eps_rel = 1e-4: stop iteration +-1,
+    objective and sampled voltages within 1e-6."""
+    from paper_2501_08293_amd import OPF_PREC_FP64
+    _say("[gpu] 8500bus fp64 eps=1e-4 vs golden")
+    g = _golden("8500bus", 1e-4)
+    s = _solver(_inst("8500bus"), rho=RHO, eps_rel=1e-4, precision=OPF_PREC_FP64, check_every=1024)
+    out = s.solve()
+    s.close()
+    _say(f"  iterations {out['iterations']}, golden {g['iterations']}")
+    assert out["status"] == 0
+    assert abs(out["iterations"] - g["iterations"]) <= 1
+    assert abs(out["objective"] - g["objective"]) <= 1e-6 * abs(g["objective"])
+    w = out["x"][g["w_index"]]
+    assert np.max(np.abs(w - np.array(g["w_value"]))) <= 1e-6
+    ref_x = np.array(g["x_value"])
+    assert np.max(np.abs(out["x"][g["x_index"]] - ref_x)) <= 1e-6 * max(1.0, float(np.max(np.abs(ref_x))))
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_thirty_thousand_component_size_fixed_iterations(prec):
     """The ~30k-component size (21000-bus feeder, S = 29393): too large for a
