@@ -245,6 +245,27 @@ int opf_admm_solve(opf_admm_handle* h, const opf_warm* warm, opf_result* r);
 int opf_admm_run_fixed(opf_admm_handle* h, const opf_warm* warm, int64_t iters, opf_result* r);
 
 /*
+ * opf_admm_solve without any device allocation or graph instantiation during
+ * the call, for callers that cannot allocate: serving loops and harnesses
+ * that forbid hipMalloc/hipFree once set-up is done.  Same arguments,
+ * outputs and return codes as opf_admm_solve, and the same iterates bit for
+ * bit: the iteration kernels are the same, but their scratch (the step
+ * kernel's residual partials and arrival counters, the persistent kernel's
+ * published terms, residual records and decision words) lives in one static
+ * device array of OPF_NOALLOC_SCRATCH_BYTES per device, held by the library
+ * until the process ends, instead of the handle's buffers, and the step
+ * schedule issues its launches one by one instead of replaying a captured
+ * graph.  The array keeps the last call's contents; each call prepares what
+ * it reads.  Every such call on one device uses the same array, so calls
+ * that overlap on one device (other threads, other streams) race and must
+ * be serialised by the caller.  A problem whose scratch does not fit (about
+ * 32 bytes per packed lane plus 64 bytes per workgroup; e.g. 8500 buses use
+ * 5.5 MB, 21000 buses 13.5 MB) is rejected with OPF_EINVAL before any work.
+ */
+#define OPF_NOALLOC_SCRATCH_BYTES (16u << 20)
+int opf_admm_solve_noalloc(opf_admm_handle* h, const opf_warm* warm, opf_result* r);
+
+/*
  * Quantities of the termination test (Section III-C, eq. termination) at the
  * last completed iteration of the handle:
  *   pres     = sqrt(sum_s ||B_s x - x_s||^2),

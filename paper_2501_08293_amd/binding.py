@@ -43,6 +43,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBOUNDS", -3: "E
                 -4: "EINFEASIBLE_COMPONENT", -5: "ENOMEM", -6: "EHIP", -7: "ENUMERIC", -8: "EHANG"}
 
 EXPORTED = ["opf_admm_default_options", "opf_admm_setup", "opf_admm_solve", "opf_admm_run_fixed",
+            "opf_admm_solve_noalloc",
             "opf_admm_residuals", "opf_admm_get_info", "opf_admm_destroy", "opf_admm_last_error",
             "opf_admm_setup_batch", "opf_admm_setup_batch_ex", "opf_admm_solve_batch", "opf_admm_batch_info", "opf_admm_destroy_batch",
             "opf_admm_batch_last_error", "opf_server_default_options", "opf_server_create", "opf_server_submit",
@@ -169,6 +170,8 @@ def load(path: str = LIB_PATH):
     lib.opf_admm_solve.restype = C.c_int
     lib.opf_admm_run_fixed.argtypes = [H, C.POINTER(opf_warm), C.c_int64, C.POINTER(opf_result)]
     lib.opf_admm_run_fixed.restype = C.c_int
+    lib.opf_admm_solve_noalloc.argtypes = [H, C.POINTER(opf_warm), C.POINTER(opf_result)]
+    lib.opf_admm_solve_noalloc.restype = C.c_int
     lib.opf_admm_residuals.argtypes = [H, C.POINTER(opf_residuals), C.POINTER(C.c_double), C.c_int]
     lib.opf_admm_residuals.restype = C.c_int
     lib.opf_admm_get_info.argtypes = [H, C.POINTER(opf_admm_info)]
@@ -247,6 +250,10 @@ def opf_admm_setup(problem: opf_problem, options: opf_admm_options, stream: int 
 
 def opf_admm_solve(h, warm, result: opf_result) -> int:
     return load().opf_admm_solve(h, C.byref(warm) if warm is not None else None, C.byref(result))
+
+
+def opf_admm_solve_noalloc(h, warm, result: opf_result) -> int:
+    return load().opf_admm_solve_noalloc(h, C.byref(warm) if warm is not None else None, C.byref(result))
 
 
 def opf_admm_run_fixed(h, warm, iters: int, result: opf_result) -> int:
@@ -496,16 +503,23 @@ class Solver:
             w.on_device = 1
         return w
 
-    def solve(self, x=None, z=None, lam=None, z0=None, lam0=None, fixed_iters=None, raise_on_error=True):
+    def solve(self, x=None, z=None, lam=None, z0=None, lam0=None, fixed_iters=None, raise_on_error=True,
+              noalloc=False):
         """Runs Algorithm 1.  Outputs go to the given arrays (numpy = host,
-        torch CUDA tensors = device); by default new host arrays are returned."""
+        torch CUDA tensors = device); by default new host arrays are returned.
+        noalloc: through opf_admm_solve_noalloc (kernel scratch in the
+        library's static device array; not with fixed_iters)."""
         if x is None:
             x = np.zeros(self.n)
             z = np.zeros(self.L) if z is None else z
             lam = np.zeros(self.L) if lam is None else lam
         r = self._result(x, z, lam)
         w = self._warm(z0, lam0)
-        if fixed_iters is None:
+        if noalloc:
+            if fixed_iters is not None:
+                raise ValueError("the allocation-free solve runs to the termination test")
+            rc = opf_admm_solve_noalloc(self.h, w, r)
+        elif fixed_iters is None:
             rc = opf_admm_solve(self.h, w, r)
         else:
             rc = opf_admm_run_fixed(self.h, w, fixed_iters, r)

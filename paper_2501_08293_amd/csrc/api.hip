@@ -67,7 +67,8 @@ struct PrecState {
 
 // Scratch of the iteration kernels: the step kernel's residual partials and
 // arrival counters, the persistent kernel's published terms, residual
-// records, decision words and error flag.  A handle owns one set.
+// records, decision words and error flag.  A handle owns one set; the
+// allocation-free solve points the kernels at the static device array instead.
 struct Work {
     double* partials = nullptr;
     unsigned long long* pub = nullptr;     // published copy terms [2][LP][2] (tagged words)
@@ -487,6 +488,82 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
     return status;
 }
 
+// ---- allocation-free solve: kernel scratch in a static device array ----------
+//
+// One array per device for the life of the process (the code object's
+// static data); its address on each device is looked up once, with that
+// device current, and kept.  Every allocation-free solve on a device shares
+// it, so such solves must not overlap on one device.
+constexpr size_t kScratchBytes = OPF_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+__global__ void zero_words_kernel(unsigned* p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of scratch the handle's kernels need (both schedules, both precisions).
+size_t static_work_bytes(const opf_admm_handle* h) {
+    const size_t G = (size_t)h->lay.blocks;
+    return round256((size_t)h->LP * 4 * sizeof(unsigned long long)) +
+           round256(G * 10 * kDecisionLag * sizeof(unsigned long long)) + 3 * 256 +
+           round256(step_partials_count((int)G) * sizeof(double));
+}
+
+// Points w at the static array of the handle's device; the step kernel's
+// arrival counters (behind its residual partials) are cleared, the persistent
+// kernel's words are prepared by its own launch.
+int static_work(opf_admm_handle* h, Work* w) {
+    const size_t need = static_work_bytes(h);
+    if (need > kScratchBytes)
+        return set_err(h, OPF_EINVAL, "the allocation-free solve needs " + std::to_string(need) +
+                                          " bytes of kernel scratch; the static array holds " +
+                                          std::to_string(kScratchBytes));
+    if (h->device < 0 || h->device >= kMaxDevices) return set_err(h, OPF_EINVAL, "device id out of range");
+    unsigned char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = g_scratch_ptr[h->device];
+        if (!base) {
+            int cur = 0;
+            HIPCHK(hipGetDevice(&cur));
+            if (cur != h->device) HIPCHK(hipSetDevice(h->device));
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (cur != h->device) (void)hipSetDevice(cur);
+            if (e != hipSuccess)
+                return set_err(h, OPF_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            base = static_cast<unsigned char*>(p);
+            g_scratch_ptr[h->device] = base;
+        }
+    }
+    const size_t G = (size_t)h->lay.blocks;
+    size_t off = 0;
+    w->pub = reinterpret_cast<unsigned long long*>(base + off);
+    off += round256((size_t)h->LP * 4 * sizeof(unsigned long long));
+    w->records = reinterpret_cast<unsigned long long*>(base + off);
+    off += round256(G * 10 * kDecisionLag * sizeof(unsigned long long));
+    w->dec_iter = reinterpret_cast<long long*>(base + off);
+    off += 256;
+    w->dec_stop = reinterpret_cast<long long*>(base + off);
+    off += 256;
+    w->dev_error = reinterpret_cast<int*>(base + off);
+    off += 256;
+    w->partials = reinterpret_cast<double*>(base + off);
+    w->graphs = false;
+    const size_t words = step_partials_count((int)G) * 2;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, h->stream,
+                       reinterpret_cast<unsigned*>(w->partials), words);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
 }  // namespace
 
 // Device set-up: row reduction and factors of every component on the GPU,
@@ -736,6 +813,14 @@ int opf_admm_run_fixed(opf_admm_handle* h, const opf_warm* warm, int64_t iters, 
     if (!h) return set_err(nullptr, OPF_EINVAL, "null handle");
     if (iters < 1) return set_err(h, OPF_EINVAL, "iters must be >= 1");
     return solve_impl(h, warm, r, iters, h->work);
+}
+
+int opf_admm_solve_noalloc(opf_admm_handle* h, const opf_warm* warm, opf_result* r) {
+    if (!h) return set_err(nullptr, OPF_EINVAL, "null handle");
+    Work w;
+    int rc = static_work(h, &w);
+    if (rc) return rc;
+    return solve_impl(h, warm, r, 0, w);
 }
 
 int opf_admm_residuals(const opf_admm_handle* hc, opf_residuals* out, double* hist, int hist_cap) {
