@@ -152,7 +152,16 @@ typedef struct opf_admm_options {
     double  rho_tau;        /* > 1 */
     double  rho_min;        /* 0 < rho_min <= rho */
     double  rho_max;        /* rho <= rho_max */
-    int32_t reserved[2];
+    /* Several local updates per global update, the second acceleration
+       Section III-D points to: with x fixed, the local update closed_2 and
+       the dual update ADMM-3 are repeated local_updates times.  In the
+       projection form the duals lie in the row space of A_s after a dual
+       update, so the repeated projections return the same local copies and
+       k repetitions equal one local update followed by a dual step of
+       length k rho, which is how the kernels run them.  The residuals keep
+       rho.  0 or 1 = one local update (Algorithm 1). */
+    int32_t local_updates;
+    int32_t reserved[1];
 } opf_admm_options;
 
 #define OPF_RHO_RELATIVE 0

@@ -268,7 +268,7 @@ def balance_factor(pres, dres, eps_prim, eps_dual, mu, tau, relative=True):
 
 def solve(P: Problem, rho: float = 100.0, eps_rel: float = 1e-3, max_iter: int = 1_000_000,
           z0=None, lam0=None, fixed_iters: int | None = None, record=True, progress=None,
-          balance=None) -> Result:
+          balance=None, local_updates: int = 1) -> Result:
     """Algorithm 1: global update, then local and dual updates, until the
     termination test holds (or max_iter / fixed_iters iterations).
 
@@ -281,7 +281,13 @@ def solve(P: Problem, rho: float = 100.0, eps_rel: float = 1e-3, max_iter: int =
     iteration t is one plain ADMM iteration with penalty rho_t: its global,
     local and dual updates and its dual residual all use rho_t.  The duals are
     kept unscaled, so a change of rho needs no rescaling of lambda, and the
-    projection factors do not depend on rho."""
+    projection factors do not depend on rho.
+
+    local_updates = k repeats, with the global x of the iteration fixed, the
+    local update and the dual update k times (several local updates per
+    global update, the second acceleration Section III-D points to); the
+    residuals compare the local copies of the iteration with those of the
+    previous one."""
     if z0 is None:
         z, lam = initial_point(P)
     else:
@@ -302,8 +308,9 @@ def solve(P: Problem, rho: float = 100.0, eps_rel: float = 1e-3, max_iter: int =
         z_prev = z
         rt = sched[t + 1]
         x = global_update(P, z, lam, rt)
-        z = local_update(P, x, lam, rt)
-        lam = dual_update(P, x, z, lam, rt)
+        for _ in range(local_updates):
+            z = local_update(P, x, lam, rt)
+            lam = dual_update(P, x, z, lam, rt)
         t += 1
         r = residuals(P, x, z, z_prev, lam, rt, eps_rel)
         nxt = sched[t + lag - 1]

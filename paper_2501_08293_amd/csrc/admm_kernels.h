@@ -165,9 +165,10 @@ struct IterArgs {
     double* hist;               // [hist_cap][4]
     int hist_cap;
     int waves;
-    T rho, inv_rho;
-    double rho_d, eps_rel;
+    T rho, inv_rho;             // rho: the dual step length (local_updates x penalty)
+    double rho_d, eps_rel;      // rho_d: the penalty
     RhoRule rule;               // rule.every == 0: rho fixed at rho_d
+    double local_updates;       // local updates per global update (dual step = local_updates x penalty)
 };
 
 // Extra state of the persistent kernel (see admm_persistent.hip).

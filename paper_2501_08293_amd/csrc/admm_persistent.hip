@@ -138,9 +138,10 @@ struct InstanceView {
     int check;
     int lds_factors;           // 0: factors read from memory; otherwise 1 (every workgroup's factors
                                // fit the launch's LDS), or with per-workgroup checks the column budget
-    T rho, inv_rho;
+    T rho, inv_rho;            // rho: the dual step length (local_updates x penalty)
     double rho_d, eps_rel;
     RhoRule rule;              // rule.every == 0: fixed penalty; else the ring of ctrl->rho
+    double local_updates;
     long long max_iter;
     long long chunk;           // the launch ends for this solve after this many iterations
 };
@@ -339,7 +340,7 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
     T inv_rho = a.inv_rho, rho = a.rho;
     if (ADAPT) {
         const double r0 = ld_agent(&ctrl->rho[(t0 + 1) % kRhoRing]);
-        rho = (T)r0;
+        rho = (T)(a.local_updates * r0);
         inv_rho = (T)(1.0 / r0);
     }
     // state of the last LAG iterations: index 0 = current iteration t
@@ -505,7 +506,7 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
             st_agent(rw + G, two[1]);
         }
         if (ADAPT) {
-            rho = (T)rho_next;
+            rho = (T)(a.local_updates * rho_next);
             inv_rho = inv_next;
         }
         t = tn;
@@ -521,7 +522,8 @@ __device__ __forceinline__ InstanceView<T> view_of(const IterArgs<T>& a, const P
     v.pub = p.pub; v.records = p.records; v.dec_iter = p.dec_iter; v.dec_stop = p.dec_stop;
     v.ctrl = a.ctrl; v.hist = a.hist; v.hist_cap = a.hist_cap; v.waves = a.waves; v.check = p.check;
     v.lds_factors = p.lds_factors; v.rho = a.rho; v.inv_rho = a.inv_rho; v.rho_d = a.rho_d;
-    v.eps_rel = a.eps_rel; v.rule = a.rule; v.max_iter = p.max_iter; v.chunk = 0x3fffffffffffffffll;
+    v.eps_rel = a.eps_rel; v.rule = a.rule; v.local_updates = a.local_updates; v.max_iter = p.max_iter;
+    v.chunk = 0x3fffffffffffffffll;
     return v;
 }
 
@@ -569,7 +571,7 @@ __device__ __forceinline__ InstanceView<T> view_of(const InstDesc& D, const Serv
     v.pub = D.pub; v.records = D.records; v.dec_iter = D.dec; v.dec_stop = D.dec + 1;
     v.ctrl = D.ctrl; v.hist = nullptr; v.hist_cap = 0; v.waves = D.lanes / 64; v.check = D.ctrl->check;
     v.lds_factors = s.lds_cols; v.rho = (T)D.rho; v.inv_rho = (T)(1.0 / D.rho); v.rho_d = D.rho;
-    v.eps_rel = D.eps_rel; v.rule = RhoRule{0, 0, 0.0, 0.0, 0.0, 0.0};
+    v.eps_rel = D.eps_rel; v.rule = RhoRule{0, 0, 0.0, 0.0, 0.0, 0.0}; v.local_updates = 1.0;
     v.max_iter = D.ctrl->max_iter; v.chunk = s.chunk;
     return v;
 }

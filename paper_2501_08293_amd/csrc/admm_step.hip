@@ -150,7 +150,7 @@ __global__ __launch_bounds__(WPB * 64) void admm_step_kernel(IterArgs<T> a) {
     double rho_d = a.rho_d;
     if (a.rule.every) {
         rho_d = ctrl->rho[t % kRhoRing];
-        rho = (T)rho_d;
+        rho = (T)(a.local_updates * rho_d);
         inv_rho = (T)(1.0 / rho_d);
     }
 

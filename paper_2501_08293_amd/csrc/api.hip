@@ -237,8 +237,9 @@ IterArgs<T> iter_args(opf_admm_handle* h, PrecState<T>& s, const Work& w) {
     a.hist = h->hist;
     a.hist_cap = h->opt.history_cap;
     a.waves = h->lay.waves;
-    a.rho = (T)h->opt.rho;
+    a.rho = (T)(h->opt.local_updates * h->opt.rho);    // dual step length
     a.inv_rho = (T)(1.0 / h->opt.rho);
+    a.local_updates = (double)h->opt.local_updates;
     a.rho_d = h->opt.rho;
     a.eps_rel = h->opt.eps_rel;
     a.rule = RhoRule{h->opt.rho_every, h->opt.rho_mode, h->opt.rho_mu, h->opt.rho_tau, h->opt.rho_min,
@@ -682,6 +683,8 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
         return set_err(nullptr, OPF_EINVAL, "unknown precision");
     if (opt.history_cap < 0) return set_err(nullptr, OPF_EINVAL, "history_cap must be >= 0");
     if (opt.rho_every < 0) return set_err(nullptr, OPF_EINVAL, "rho_every must be >= 0");
+    if (opt.local_updates < 0) return set_err(nullptr, OPF_EINVAL, "local_updates must be >= 0");
+    if (opt.local_updates == 0) opt.local_updates = 1;
     if (opt.rho_every > 0) {
         if (opt.rho_mu == 0.0) opt.rho_mu = 10.0;
         if (opt.rho_tau == 0.0) opt.rho_tau = 2.0;

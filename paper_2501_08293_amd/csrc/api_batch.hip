@@ -152,8 +152,9 @@ int opf_admm_setup_batch_ex(const opf_problem* p, const double* b_scen, int32_t 
     else opf_admm_default_options(&opt);
     if (!(opt.rho > 0.0) || !(opt.eps_rel > 0.0) || opt.max_iter < 1)
         return berr(nullptr, OPF_EINVAL, "rho, eps_rel and max_iter must be positive");
-    if (opt.rho_every != 0)
-        return berr(nullptr, OPF_EINVAL, "the batched path runs a fixed penalty (rho_every must be 0)");
+    if (opt.rho_every != 0 || opt.local_updates > 1)
+        return berr(nullptr, OPF_EINVAL, "the batched path runs Algorithm 1 with a fixed penalty "
+                                         "(rho_every 0, one local update)");
     if (opt.check_every < 1) opt.check_every = 64;
     auto t0 = std::chrono::steady_clock::now();
     opf_admm_batch* h = new opf_admm_batch();

@@ -709,8 +709,9 @@ int opf_server_create(const opf_server_options* o, void* hip_stream, opf_server*
         opt.max_slots < 1 || opt.max_workgroups < 1 || opt.iters_per_poll < 1 ||
         (opt.admm.precision != OPF_PREC_FP64 && opt.admm.precision != OPF_PREC_MIXED))
         return serr(nullptr, OPF_EINVAL, "invalid server options");
-    if (opt.admm.rho_every != 0)
-        return serr(nullptr, OPF_EINVAL, "served solves run a fixed penalty (rho_every must be 0)");
+    if (opt.admm.rho_every != 0 || opt.admm.local_updates > 1)
+        return serr(nullptr, OPF_EINVAL, "served solves run Algorithm 1 with a fixed penalty "
+                                         "(rho_every 0, one local update)");
     auto s = std::make_unique<opf_server>();
     s->opt = opt;
     if (opt.setup_threads < 1) s->opt.setup_threads = 1;

@@ -61,7 +61,7 @@ def inst():
 
 @pytest.mark.parametrize("kw", [dict(rho_every=-1), dict(rho_every=5, rho_tau=1.0), dict(rho_every=5, rho_mu=0.5),
                                 dict(rho_every=5, rho_min=200.0), dict(rho_every=5, rho_max=50.0),
-                                dict(rho_every=5, rho_mode=7)])
+                                dict(rho_every=5, rho_mode=7), dict(local_updates=-1)])
 def test_rejects_invalid_balancing_options(inst, kw):
     binding, _ = _lib()
     with pytest.raises(binding.OpfError) as e:
@@ -74,6 +74,10 @@ def test_server_rejects_balancing():
     o = binding.opf_server_default_options()
     o.admm.rho_every = 10
     h = C.c_void_p()
+    assert lib.opf_server_create(C.byref(o), None, C.byref(h)) == binding.OPF_EINVAL
+    assert not h.value
+    o = binding.opf_server_default_options()
+    o.admm.local_updates = 2
     assert lib.opf_server_create(C.byref(o), None, C.byref(h)) == binding.OPF_EINVAL
     assert not h.value
 

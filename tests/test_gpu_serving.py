@@ -245,3 +245,33 @@ def test_mixed_precision_serving_stall_watch(mix):
         assert r["pres"] <= r["eps_prim"] and r["dres"] <= r["eps_dual"]
         assert r["iterations"] == one["iterations"] and r["iterations_fp32"] == one["iterations_fp32"]
         assert np.array_equal(r["x"], one["x"])
+
+
+def test_warm_started_solve_alone_and_in_mix_give_identical_bits(mix):
+    """A warm start draws on the resident state of its family; with that state
+    fixed (the family's previous solve retired before the request arrives),
+    the warm-started solve returns the same bits alone and in a mix of other
+    solves, in mixed precision."""
+    from paper_2501_08293_amd import OPF_PREC_MIXED, Server
+    _say("[gpu] serving: warm-started solve alone vs in a mix of six (mixed precision)")
+    fam = make_family(7, 0, n_bus=300)
+    rng = np.random.default_rng(11)
+    base = build_instance(fam.base)
+    nxt = build_instance(with_loads(reconfigure(fam, 0, rng), rng))
+    kw = dict(rho=RHO, eps_rel=1e-4, warm_start=True, iters_per_poll=64, arena_bytes=256 << 20,
+              precision=OPF_PREC_MIXED)
+    out = []
+    for others in ([], mix):
+        srv = Server(**kw)
+        r0 = srv.submit(*_args(base), family=7, comp_keys=component_keys(base))
+        _drain(srv, [r0])
+        r1 = srv.submit(*_args(nxt), family=7, comp_keys=component_keys(nxt))
+        ids = [srv.submit(*_args(inst), family=100 + k) for k, inst in enumerate(others)]
+        res = _drain(srv, [r1] + ids)
+        srv.close()
+        assert all(res[i]["status"] == 0 for i in [r1] + ids)
+        out.append(res[r1])
+    alone, inmix = out
+    assert alone["warm_components"] > 0 and alone["warm_components"] == inmix["warm_components"]
+    assert alone["iterations"] == inmix["iterations"] and alone["iterations_fp32"] == inmix["iterations_fp32"]
+    assert np.array_equal(alone["x"], inmix["x"])
