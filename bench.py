@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--eps", type=float, default=1e-4)
-    ap.add_argument("--kernel", default="auto", choices=["auto", "step", "persistent"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "step", "persistent", "tiled"])
     ap.add_argument("--block-waves", type=int, default=0)
     ap.add_argument("--workgroup-order", type=int, default=0, choices=[0, 1],
                     help="persistent kernel: 0 = hardware workgroup order, 1 = XCD-contiguous packing ranges")
@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--batch-workload", default="2500bus")
     ap.add_argument("--batch-k", type=int, default=256)
+    ap.add_argument("--batch-fixed", type=int, default=0,
+                    help="run this many batch iterations instead of solving to tolerance (counter passes)")
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--serve-families", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -202,7 +204,7 @@ def single_instance(args, torch):
     gen_s = time.perf_counter() - t0
     stream = torch.cuda.Stream()
     prec = OPF_PREC_MIXED if args.precision == "mixed" else OPF_PREC_FP64
-    kern = {"auto": 0, "step": 1, "persistent": 2}[args.kernel]
+    kern = {"auto": 0, "step": 1, "persistent": 2, "tiled": 3}[args.kernel]
     flat = (inst.n, inst.c, inst.lb, inst.ub, inst.var_kind) + tuple(inst.flat())
     solver = Solver(*flat, rho=100.0, eps_rel=args.eps, precision=prec, check_every=args.check_every,
                     kernel=kern, block_waves=args.block_waves, workgroup_order=args.workgroup_order,
@@ -238,9 +240,11 @@ def single_instance(args, torch):
     else:
         dom_name, dom_bytes, dom_ms, dom_iters = "admm_persistent_kernel<double, 4>", bpi64, k64, it64
     dom_launches = args.steps
-    if info.kernel != 2:
+    if info.kernel == 1:
         dom_name = dom_name.replace("persistent", "step")
         dom_launches = dom_iters
+    elif info.kernel == 3:
+        dom_name = dom_name.replace("persistent", "tiled")
     achieved = dom_bytes * dom_iters / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     tr = traffic_from_profiles(args.workload, args.precision)
     traffic = None
@@ -273,7 +277,7 @@ def single_instance(args, torch):
             "generator_s": round(gen_s, 2),
             "waves": info.waves,
             "lanes": info.lanes,
-            "kernel": {1: "step", 2: "persistent"}.get(info.kernel, "?"),
+            "kernel": {1: "step", 2: "persistent", 3: "tiled"}.get(info.kernel, "?"),
             "block_waves": info.block_waves,
             "workgroups": info.grid_blocks,
             "factors_in_lds": info.factors_in_lds,
@@ -327,7 +331,7 @@ def solve_leg(workload, precision, eps, torch, steps=1, fixed=None, **kw):
     out = {"workload": f"{inst.name}: S={inst.S}, n={inst.n}, L={inst.L}", "precision": precision,
            "eps_rel": eps, "status": int(r["status"]), "iterations": it, "iterations_fp32": int(r["iterations_fp32"]),
            "ms": round(1e3 * wall, 3), "iters_per_s": round(it / wall, 1),
-           "kernel": {1: "step", 2: "persistent"}.get(info.kernel, "?"), "workgroups": info.grid_blocks,
+           "kernel": {1: "step", 2: "persistent", 3: "tiled"}.get(info.kernel, "?"), "workgroups": info.grid_blocks,
            "us_per_iteration": round(1e3 * kms / max(kit, 1), 3),
            "algorithmic_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
            "objective": r["objective"]}
@@ -351,6 +355,8 @@ def more_legs(args, torch):
             legs[f"{w}_{p}"] = solve_leg(w, p, args.eps, torch, steps=5)
     legs["21000bus_mixed_fixed4096"] = solve_leg("21000bus", "mixed", args.eps, torch, fixed=4096)
     legs["21000bus_fp64_fixed4096"] = solve_leg("21000bus", "fp64", args.eps, torch, fixed=4096)
+    legs["21000bus_mixed_step_fixed4096"] = solve_leg("21000bus", "mixed", args.eps, torch, fixed=4096, kernel=1)
+    legs["21000bus_mixed"] = solve_leg("21000bus", "mixed", args.eps, torch)
     legs["8500bus_mixed_balanced"] = solve_leg("8500bus", "mixed", args.eps, torch, **BALANCE)
     return legs
 
@@ -364,8 +370,10 @@ def batch_leg(args, torch):
     K = args.batch_k
     B = scenario_rhs(inst, scenario_load_factors(f, K, seed=1000))
     st = torch.cuda.Stream()
+    fixed = args.batch_fixed > 0
     s = BatchSolver(inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, *inst.flat(), b_scen=B, rho=100.0,
-                    eps_rel=args.eps, check_every=256, stream=st.cuda_stream)
+                    eps_rel=1e-12 if fixed else args.eps, max_iter=args.batch_fixed if fixed else 1_000_000,
+                    check_every=256, stream=st.cuda_stream)
     info = s.info()
     t0 = time.perf_counter()
     out = s.solve()
@@ -407,7 +415,7 @@ def batch_leg(args, torch):
                  "frac": round(tf / BF16_DENSE_PEAK_TFLOPS, 5),
                  "useful_fraction_of_issued": round(useful_flops * 6 / max(mfma_flops, 1), 4)},
         "precision": "bf16 three-term split products on MFMA, fp32 accumulate, fp32 state, fp64 residual sums",
-        "zip_loads": zip_batch_timing(args, torch, K),
+        "zip_loads": zip_batch_timing(args, torch, K) if not fixed else None,
     }
 
 

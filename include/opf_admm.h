@@ -69,6 +69,10 @@ extern "C" {
 #define OPF_KERNEL_AUTO        0
 #define OPF_KERNEL_STEP        1  /* one fused launch per iteration, host checks a device flag */
 #define OPF_KERNEL_PERSISTENT  2  /* one cooperative launch runs all iterations */
+#define OPF_KERNEL_TILED       3  /* one cooperative launch runs all iterations with fewer workgroups
+                                     than the packing has: each takes several workgroup tiles in turn,
+                                     state kept in memory (AUTO picks it when the persistent grid does
+                                     not fit the device; fixed penalty only) */
 
 /*
  * Problem data: the componentwise LP of OurModel.
@@ -161,7 +165,9 @@ typedef struct opf_admm_options {
        length k rho, which is how the kernels run them.  The residuals keep
        rho.  0 or 1 = one local update (Algorithm 1). */
     int32_t local_updates;
-    int32_t reserved[1];
+    int32_t tiled_workgroups; /* TILED: compute workgroups of the launch (0 = the fewest that hold every
+                               tile with an even share, limited by what the device holds at once);
+                               fewer workgroups take more tiles each */
 } opf_admm_options;
 
 #define OPF_RHO_RELATIVE 0
@@ -211,7 +217,8 @@ typedef struct opf_admm_info {
     int64_t factor_bytes_fp64; /* device bytes of the packed FP64 factors */
     int64_t device_bytes;      /* all device memory owned by the handle */
     double  setup_ms;          /* host factorisation + packing + upload */
-    int32_t grid_blocks;       /* workgroups of the iteration kernels */
+    int32_t grid_blocks;       /* compute workgroups of the iteration kernels (TILED: of the launch; the
+                                  packing's workgroup tiles are grid_blocks of the other schedules) */
     int32_t block_waves;       /* wavefronts per workgroup */
     int32_t kernel;            /* OPF_KERNEL_STEP or OPF_KERNEL_PERSISTENT, as selected */
     int32_t persistent_capacity;   /* co-resident workgroups the device can hold */

@@ -34,6 +34,7 @@ OPF_PREC_MIXED = 1
 OPF_KERNEL_AUTO = 0
 OPF_KERNEL_STEP = 1
 OPF_KERNEL_PERSISTENT = 2
+OPF_KERNEL_TILED = 3
 
 OPF_RHO_RELATIVE = 0
 OPF_RHO_PLAIN = 1
@@ -65,7 +66,7 @@ class opf_admm_options(C.Structure):
                 ("spin_limit", C.c_int32), ("split_terms", C.c_int32), ("autotune", C.c_int32),
                 ("workgroup_order", C.c_int32), ("setup_on_device", C.c_int32), ("rho_every", C.c_int32),
                 ("rho_mode", C.c_int32), ("rho_mu", C.c_double), ("rho_tau", C.c_double), ("rho_min", C.c_double),
-                ("rho_max", C.c_double), ("local_updates", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("rho_max", C.c_double), ("local_updates", C.c_int32), ("tiled_workgroups", C.c_int32)]
 
 
 class opf_warm(C.Structure):
@@ -414,7 +415,7 @@ class Solver:
                  eps_rel=1e-3, max_iter=1_000_000, precision=OPF_PREC_FP64, polish=True, check_every=256,
                  kernel=OPF_KERNEL_AUTO, history_cap=0, block_waves=0, spin_limit=0, autotune=False,
                  workgroup_order=0, setup_on_device=False, rho_every=0, rho_mode=OPF_RHO_RELATIVE, rho_mu=0.0,
-                 rho_tau=0.0, rho_min=0.0, rho_max=0.0, local_updates=1, stream=0):
+                 rho_tau=0.0, rho_min=0.0, rho_max=0.0, local_updates=1, tiled_workgroups=0, stream=0):
         self._keep = dict(
             c=np.ascontiguousarray(c, np.float64), lb=np.ascontiguousarray(lb, np.float64),
             ub=np.ascontiguousarray(ub, np.float64), var_kind=np.ascontiguousarray(var_kind, np.uint8),
@@ -450,6 +451,7 @@ class Solver:
         o.rho_min = rho_min
         o.rho_max = rho_max
         o.local_updates = local_updates
+        o.tiled_workgroups = tiled_workgroups
         self.options = o
         self.h = opf_admm_setup(p, o, stream)
         self._keep = None   # the library copied everything it needs

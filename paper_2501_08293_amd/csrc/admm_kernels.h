@@ -186,6 +186,18 @@ struct PersistArgs {
     int xcd_remap;              // 1: consecutive workgroups of the packing share an XCD
 };
 
+// Extra state of the tiled persistent schedule (see admm_persistent.hip): the
+// state of the last kStateRing iterations, in the iteration kernel's element
+// type, and the number of workgroup tiles of the packing.
+constexpr int kStateRing = 4;
+struct TiledArgs {
+    void* zr;                   // [kStateRing][LP] local copies
+    void* lr;                   // [kStateRing][LP] duals
+    void* xr;                   // [kStateRing][n] global variables (written by owner slots)
+    int tiles;                  // workgroup tiles of the packing (block_waves wavefronts each)
+    int n;
+};
+
 // Iterations between a residual reduction and the moment workgroups act on
 // its stop decision (also the depth of the partial-sum ring and of the state
 // history each slot keeps in registers).

@@ -31,6 +31,9 @@ template <typename T>
 hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G, hipStream_t st);
 template <typename T> int persistent_capacity(int wpb, size_t lds_bytes, int adapt);
 template <typename T>
+hipError_t launch_tiled(const IterArgs<T>& a, PersistArgs p, const TiledArgs& ta, int wpb, int G, hipStream_t st);
+template <typename T> int tiled_capacity(int wpb);
+template <typename T>
 hipError_t launch_output(const T* z0, const T* z1, const T* l0, const T* l1, const T* x0, const T* x1,
                          const int* user_slot, int LP, int n, const double* c, double* xo, double* zo,
                          double* lo, Ctrl* ctrl, hipStream_t st);
@@ -63,6 +66,9 @@ struct PrecState {
     T* z[2] = {nullptr, nullptr};
     T* l[2] = {nullptr, nullptr};
     T* x[2] = {nullptr, nullptr};
+    T* zr = nullptr;                 // tiled schedule: state of the last kStateRing iterations
+    T* lr = nullptr;
+    T* xr = nullptr;
 };
 
 // Scratch of the iteration kernels: the step kernel's residual partials and
@@ -125,6 +131,7 @@ struct opf_admm_handle {
     // persistent schedule
     int kernel = OPF_KERNEL_STEP;
     int capacity = 0;
+    int tiled_G = 0;               // tiled schedule: compute workgroups (tiles = lay.blocks)
     Work work;                     // the handle's own kernel scratch
     int xcd_remap = 1;
     int* error_host = nullptr;     // pinned
@@ -200,6 +207,11 @@ int make_prec(opf_admm_handle* h, PrecState<T>& s) {
     if ((rc = upload(h, &s.lo, L.lo))) return rc;
     if ((rc = upload(h, &s.hi, L.hi))) return rc;
     if ((rc = upload(h, &s.cost, L.cost))) return rc;
+    if (h->kernel == OPF_KERNEL_TILED) {
+        if ((rc = dalloc(h, &s.zr, (size_t)kStateRing * h->LP))) return rc;
+        if ((rc = dalloc(h, &s.lr, (size_t)kStateRing * h->LP))) return rc;
+        if ((rc = dalloc(h, &s.xr, (size_t)kStateRing * L.n))) return rc;
+    }
     for (int b = 0; b < 2; ++b) {
         if ((rc = dalloc(h, &s.z[b], h->LP))) return rc;
         if ((rc = dalloc(h, &s.l[b], h->LP))) return rc;
@@ -349,9 +361,48 @@ int run_phase_persistent(opf_admm_handle* h, PrecState<T>& s, long long max_iter
 }
 
 template <typename T>
+int run_phase_tiled(opf_admm_handle* h, PrecState<T>& s, long long max_iter, int check, const Work& w) {
+    IterArgs<T> a = iter_args(h, s, w);
+    PersistArgs p;
+    p.pub = w.pub;
+    p.records = w.records;
+    p.dec_iter = w.dec_iter;
+    p.dec_stop = w.dec_stop;
+    p.error = w.dev_error;
+    p.xcd_remap = 0;
+    p.spin_limit = h->opt.spin_limit > 0 ? h->opt.spin_limit : 4000000LL;
+    p.max_iter = max_iter;
+    p.check = check;
+    p.lds_factor_cols = 0;
+    p.lds_factors = 0;
+    TiledArgs ta;
+    ta.zr = s.zr;
+    ta.lr = s.lr;
+    ta.xr = s.xr;
+    ta.tiles = h->lay.blocks;
+    ta.n = h->lay.n;
+    HIPCHK(hipEventRecord(h->ev0, h->stream));
+    HIPCHK(launch_tiled<T>(a, p, ta, h->wpb, h->tiled_G, h->stream));
+    HIPCHK(hipEventRecord(h->ev1, h->stream));
+    HIPCHK(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(h->error_host, w.dev_error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->kernel_ms += ms;
+    h->kernel_launches += 1;
+    if (*h->error_host) {
+        h->ctrl_host->status = OPF_EHANG;
+        return set_err(h, OPF_EHANG, "a bounded device-side wait ran out in the tiled persistent kernel");
+    }
+    return 0;
+}
+
+template <typename T>
 int run_any(opf_admm_handle* h, PrecState<T>& s, hipGraphExec_t* graph, long long max_iter, int check,
             const Work& w) {
     if (h->kernel == OPF_KERNEL_PERSISTENT) return run_phase_persistent<T>(h, s, max_iter, check, w);
+    if (h->kernel == OPF_KERNEL_TILED) return run_phase_tiled<T>(h, s, max_iter, check, w);
     return run_phase<T>(h, s, graph, w);
 }
 
@@ -790,9 +841,26 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
         return fail(set_err(h, OPF_EINVAL, "persistent kernel needs " + std::to_string(blocks + 1) +
                                               " co-resident workgroups, the device holds " +
                                               std::to_string(h->capacity)));
+    // tiled schedule: as many co-resident workgroups as needed for an even
+    // share of tiles (plus the reducer)
+    int tcap = tiled_capacity<double>(h->wpb);
+    if (opt.precision == OPF_PREC_MIXED) tcap = std::min(tcap, tiled_capacity<float>(h->wpb));
+    const bool tiled_ok = tcap >= 2 && opt.rho_every == 0;
+    if (opt.tiled_workgroups < 0) return fail(set_err(h, OPF_EINVAL, "tiled_workgroups must be >= 0"));
+    if (tiled_ok) {
+        int gmax = std::min(tcap - 1, blocks);
+        if (opt.tiled_workgroups > 0) gmax = std::min(gmax, opt.tiled_workgroups);
+        const int per = (blocks + gmax - 1) / gmax;
+        h->tiled_G = (blocks + per - 1) / per;
+    }
+    if (opt.kernel == OPF_KERNEL_TILED && !tiled_ok)
+        return fail(set_err(h, OPF_EINVAL, "the tiled schedule runs a fixed penalty on a device holding at least "
+                                           "two of its workgroups"));
     if (opt.kernel == OPF_KERNEL_STEP) h->kernel = OPF_KERNEL_STEP;
     else if (opt.kernel == OPF_KERNEL_PERSISTENT) h->kernel = OPF_KERNEL_PERSISTENT;
-    else h->kernel = (h->capacity >= blocks + 1) ? OPF_KERNEL_PERSISTENT : OPF_KERNEL_STEP;
+    else if (opt.kernel == OPF_KERNEL_TILED) h->kernel = OPF_KERNEL_TILED;
+    else if (h->capacity >= blocks + 1) h->kernel = OPF_KERNEL_PERSISTENT;
+    else h->kernel = tiled_ok ? OPF_KERNEL_TILED : OPF_KERNEL_STEP;
     if ((rc = dalloc(h, &h->hist, (size_t)std::max(1, opt.history_cap) * 4))) return fail(rc);
     if ((rc = dalloc(h, &h->ctrl, 1))) return fail(rc);
     if (hipMemsetAsync(h->ctrl, 0, sizeof(Ctrl), h->stream) != hipSuccess) return fail(set_err(h, OPF_EHIP, "memset"));
@@ -864,7 +932,7 @@ int opf_admm_get_info(const opf_admm_handle* h, opf_admm_info* info) {
     info->factor_bytes_fp64 = (int64_t)h->lay.F.size() * 8;
     info->device_bytes = (int64_t)h->device_bytes;
     info->setup_ms = h->setup_ms;
-    info->grid_blocks = h->grid_blocks;
+    info->grid_blocks = h->kernel == OPF_KERNEL_TILED ? h->tiled_G : h->grid_blocks;
     info->block_waves = h->wpb;
     info->kernel = h->kernel;
     info->persistent_capacity = h->capacity;
