@@ -30,7 +30,8 @@ HBM_PEAK_GBS = 8000.0
 BALANCE = dict(rho_every=10)
 BF16_DENSE_PEAK_TFLOPS = 2500.0
 METRIC = "8500-bus ADMM iters/s & time-to-1e-4 residual; served solves/s + p99 latency"
-KERNEL_SOURCES = ["paper_2501_08293_amd/csrc/admm_persistent.hip", "paper_2501_08293_amd/csrc/admm_kernels.h"]
+KERNEL_SOURCES = ["paper_2501_08293_amd/csrc/admm_persistent.hip", "paper_2501_08293_amd/csrc/admm_kernels.h",
+                  "paper_2501_08293_amd/csrc/admm_sync.h"]
 
 
 def algorithmic_bytes_per_iteration(sum_ns2, L, n, elem):

@@ -32,242 +32,11 @@
 #include <algorithm>
 
 #include "admm_kernels.h"
+#include "admm_sync.h"
 
 #include "../../include/opf_admm.h"
 
 namespace opf {
-
-template <typename T>
-__device__ __forceinline__ T ld_agent(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ void st_agent(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// Wait until every memory operation this thread issued has completed.
-__device__ __forceinline__ void drain_memory() {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-__device__ __forceinline__ long long wave_min_p(long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const long long u = __shfl_xor(v, o, 64);
-        v = u < v ? u : v;
-    }
-    return v;
-}
-
-// ---- tagged words: payload in the low 32 bits, iteration tag in the high 32
-typedef unsigned long long u64;
-template <typename T>
-struct Tag;
-template <>
-struct Tag<float> {
-    static constexpr int W = 1;
-    __device__ static void pack(float v, unsigned tag, u64 (&w)[1]) {
-        w[0] = (u64)__float_as_uint(v) | ((u64)tag << 32);
-    }
-    __device__ static float unpack(const u64 (&w)[1]) { return __uint_as_float((unsigned)w[0]); }
-};
-template <>
-struct Tag<double> {
-    static constexpr int W = 2;
-    __device__ static void pack(double v, unsigned tag, u64 (&w)[2]) {
-        const u64 bits = (u64)__double_as_longlong(v);
-        w[0] = (bits & 0xffffffffull) | ((u64)tag << 32);
-        w[1] = (bits >> 32) | ((u64)tag << 32);
-    }
-    __device__ static double unpack(const u64 (&w)[2]) {
-        return __longlong_as_double((long long)((w[0] & 0xffffffffull) | (w[1] << 32)));
-    }
-};
-template <int W>
-__device__ __forceinline__ bool tags_are(const u64 (&w)[W], unsigned tag) {
-    bool ok = true;
-#pragma unroll
-    for (int h = 0; h < W; ++h) ok &= (unsigned)(w[h] >> 32) == tag;
-    return ok;
-}
-template <int W>
-__device__ __forceinline__ void load_words(const u64* p, u64 (&w)[W]) {
-#pragma unroll
-    for (int h = 0; h < W; ++h) w[h] = ld_agent(p + h);
-}
-
-// A wait gives up after spin_limit polls, or early once another workgroup
-// has reported an error (checked every 1024 polls).
-__device__ __forceinline__ int wait_expired(long long spins, int* error, long long spin_limit) {
-    if (spins > spin_limit) return 1;
-    return (spins & 1023) == 0 && ld_agent(error) != 0;
-}
-
-constexpr int kCopyRegs = 8;
-constexpr int kBatch = 3;      // workgroups whose records a reducer thread loads at once
-constexpr int kRec = 10;       // words of one residual record (5 doubles, two tagged halves each)
-
-// Everything one solve's persistent loop touches, for the single-instance
-// kernel and for each solve of the serving kernel.
-template <typename T>
-struct InstanceView {
-    const T* F;
-    const int2* winfo;
-    const int* var;
-    const int* meta;
-    const int* cstart;
-    const int* ccnt;
-    const int* clist;
-    const T* bbar;
-    const T* lo;
-    const T* hi;
-    const T* cost;
-    T* z0; T* z1;
-    T* l0; T* l1;
-    T* x0; T* x1;
-    u64* pub;
-    u64* records;
-    long long* dec_iter;
-    long long* dec_stop;
-    Ctrl* ctrl;
-    double* hist;
-    int hist_cap;
-    int waves;
-    int check;
-    int lds_factors;           // 0: factors read from memory; otherwise 1 (every workgroup's factors
-                               // fit the launch's LDS), or with per-workgroup checks the column budget
-    T rho, inv_rho;            // rho: the dual step length (local_updates x penalty)
-    double rho_d, eps_rel;
-    RhoRule rule;              // rule.every == 0: fixed penalty; else the ring of ctrl->rho
-    double local_updates;
-    long long max_iter;
-    long long chunk;           // the launch ends for this solve after this many iterations
-};
-
-// Reducer workgroup of one solve: stop decisions of every iteration.  A
-// decision ends the launch for the solve when the test holds, on a NaN/Inf,
-// at max_iter, or after `chunk` iterations of this launch (a pause: the solve
-// continues in the next launch from the state written at the pause).
-template <typename T, int NT, bool ADAPT>
-__device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int* error, long long spin_limit) {
-    __shared__ double rred[NT / 64][5];
-    __shared__ int rstop;
-    // the reducer shares a compute unit with iteration workgroups: its waves
-    // issue first, so that the decisions keep pace with the iterations
-    __builtin_amdgcn_s_setprio(3);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    Ctrl* ctrl = v.ctrl;
-    for (long long u = t0 + 1;; ++u) {
-        // ---- records of iteration u of every workgroup, summed in a fixed order
-        // (per thread over q = tid, tid + NT, ..., then across lanes and waves)
-        const unsigned tag = (unsigned)u;
-        // word w of workgroup q at rec[w * G + q]: one load instruction per
-        // word covers 64 consecutive workgroups
-        const u64* rec = v.records + (size_t)(u % kDecisionLag) * G * kRec;
-        double acc5[5] = {0, 0, 0, 0, 0};
-        int bad = 0;
-        long long spins = 0;
-        for (int q0 = threadIdx.x; q0 < G; q0 += kBatch * NT) {
-            u64 wd[kBatch][kRec];
-            unsigned pending = 0;
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                const int q = q0 + k * NT;
-                if (q < G) {
-#pragma unroll
-                    for (int h = 0; h < kRec; ++h) wd[k][h] = ld_agent(rec + (size_t)h * G + q);
-                    pending |= 1u << k;
-                }
-            }
-            for (;;) {
-                unsigned stale = 0;
-#pragma unroll
-                for (int k = 0; k < kBatch; ++k)
-                    if (((pending >> k) & 1u) && !tags_are<kRec>(wd[k], tag)) stale |= 1u << k;
-                if (!stale || bad) break;
-                __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-                for (int k = 0; k < kBatch; ++k)
-                    if ((stale >> k) & 1u)
-#pragma unroll
-                        for (int h = 0; h < kRec; ++h) wd[k][h] = ld_agent(rec + (size_t)h * G + q0 + k * NT);
-                pending = stale;
-                bad = wait_expired(++spins, error, spin_limit);
-            }
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k)
-                if (q0 + k * NT < G)
-#pragma unroll
-                    for (int i = 0; i < 5; ++i) {
-                        const u64 two[2] = {wd[k][2 * i], wd[k][2 * i + 1]};
-                        acc5[i] += Tag<double>::unpack(two);
-                    }
-        }
-        if (__syncthreads_or(bad)) {
-            if (threadIdx.x == 0) st_agent(error, (int)OPF_EHANG);
-            return;
-        }
-#pragma unroll
-        for (int i = 0; i < 5; ++i) acc5[i] = wave_total(acc5[i]);
-        if (lane == 0)
-#pragma unroll
-            for (int i = 0; i < 5; ++i) rred[wv][i] = acc5[i];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double S[5] = {0, 0, 0, 0, 0};
-            for (int q = 0; q < NT / 64; ++q)
-#pragma unroll
-                for (int i = 0; i < 5; ++i) S[i] += rred[q][i];
-            const double rho_u = ADAPT ? ld_agent(&ctrl->rho[u % kRhoRing]) : v.rho_d;
-            const double pres = sqrt(S[0]);
-            const double dres = rho_u * sqrt(S[1]);
-            const double ep = v.eps_rel * fmax(sqrt(S[2]), sqrt(S[3]));
-            const double ed = v.eps_rel * sqrt(S[4]);
-            if (ADAPT) {
-                // penalty of iteration u + kRhoLag, visible before the decision of u is
-                const double nxt = rho_decide(v.rule, ld_agent(&ctrl->rho[(u + kRhoLag - 1) % kRhoRing]), u,
-                                              pres, dres, ep, ed);
-                st_agent(&ctrl->rho[(u + kRhoLag) % kRhoRing], nxt);
-                drain_memory();
-            }
-            if (u - 1 < v.hist_cap) {
-                v.hist[(u - 1) * 4 + 0] = pres;
-                v.hist[(u - 1) * 4 + 1] = dres;
-                v.hist[(u - 1) * 4 + 2] = ep;
-                v.hist[(u - 1) * 4 + 3] = ed;
-            }
-            int end = 1, finished = 1, status = OPF_OK;
-            if (!(isfinite(pres) && isfinite(dres) && isfinite(ep) && isfinite(ed))) {
-                status = OPF_ENUMERIC;
-            } else if (v.check && pres <= ep && dres <= ed) {
-                status = OPF_OK;
-            } else if (u >= v.max_iter) {
-                status = v.check ? OPF_NOT_CONVERGED : OPF_OK;
-            } else if (u >= t0 + v.chunk) {
-                finished = 0;                      // pause
-            } else {
-                end = 0;
-            }
-            if (end) {
-                ctrl->iter = u;
-                ctrl->status = status;
-                ctrl->res[0] = pres;
-                ctrl->res[1] = dres;
-                ctrl->res[2] = ep;
-                ctrl->res[3] = ed;
-                ctrl->stop = finished;
-                st_agent(v.dec_stop, u);
-                drain_memory();          // the end iteration is visible before dec_iter reaches it
-            }
-            st_agent(v.dec_iter, u);
-            rstop = end;
-        }
-        __syncthreads();
-        if (rstop) return;
-    }
-}
 
 // The persistent loop of one solve for workgroup b of its G compute
 // workgroups (b == G: its reducer).
@@ -513,230 +282,12 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
     }
 }
 
-template <typename T>
-__device__ __forceinline__ InstanceView<T> view_of(const IterArgs<T>& a, const PersistArgs& p) {
-    InstanceView<T> v;
-    v.F = a.F; v.winfo = a.winfo; v.var = a.var; v.meta = a.meta; v.cstart = a.cstart; v.ccnt = a.ccnt;
-    v.clist = a.clist; v.bbar = a.bbar; v.lo = a.lo; v.hi = a.hi; v.cost = a.cost;
-    v.z0 = a.z0; v.z1 = a.z1; v.l0 = a.l0; v.l1 = a.l1; v.x0 = a.x0; v.x1 = a.x1;
-    v.pub = p.pub; v.records = p.records; v.dec_iter = p.dec_iter; v.dec_stop = p.dec_stop;
-    v.ctrl = a.ctrl; v.hist = a.hist; v.hist_cap = a.hist_cap; v.waves = a.waves; v.check = p.check;
-    v.lds_factors = p.lds_factors; v.rho = a.rho; v.inv_rho = a.inv_rho; v.rho_d = a.rho_d;
-    v.eps_rel = a.eps_rel; v.rule = a.rule; v.local_updates = a.local_updates; v.max_iter = p.max_iter;
-    v.chunk = 0x3fffffffffffffffll;
-    return v;
-}
 
 template <typename T, int WPB, bool ADAPT>
 __global__ __launch_bounds__(WPB * 64) void admm_persistent_kernel(IterArgs<T> a, PersistArgs p) {
     const InstanceView<T> v = view_of(a, p);
     const int b = logical_block((int)blockIdx.x, (int)gridDim.x, p.xcd_remap);
     persistent_instance<T, WPB, false, ADAPT>(v, b, (int)gridDim.x - 1, p.error, p.spin_limit);
-}
-
-// Tiled persistent schedule, for packings with more workgroups than the device
-// holds at once: G compute workgroups (and the reducer) share the `tiles`
-// workgroup tiles of the packing, workgroup b taking tiles b, b + G, ... in
-// turn every iteration.  The per-slot state lives in memory, in a ring of the
-// last kStateRing iterations (a stop decision reaches the workgroups
-// kDecisionLag iterations late, so the decided iteration's state must outlive
-// two more), and static slot data and factors are read through the caches
-// every iteration; a slot is always computed by the same thread, so the ring
-// needs no synchronisation.  Exchange (tagged consensus terms), residual
-// records, reducer and decisions are those of the persistent kernel.  No wait
-// can deadlock: a workgroup finishes every tile of an iteration before it
-// starts the next, so the slowest workgroup always finds the terms it waits for.
-template <typename T, int WPB>
-__global__ __launch_bounds__(WPB * 64) void admm_tiled_kernel(IterArgs<T> a, PersistArgs p, TiledArgs ta) {
-    constexpr int NT = WPB * 64;
-    constexpr int W = Tag<T>::W;
-    constexpr int LAG = kDecisionLag;
-    const int G = (int)gridDim.x - 1;
-    const int b = (int)blockIdx.x;
-    int* error = p.error;
-    Ctrl* ctrl = a.ctrl;
-    const long long t0 = ctrl->iter;
-    if (b == G) {
-        const InstanceView<T> v = view_of(a, p);
-        reducer_loop<T, NT, false>(v, G, t0, error, p.spin_limit);
-        return;
-    }
-    __shared__ T vsh[WPB][64];
-    __shared__ double red[WPB][5];
-    __shared__ int sh_flag;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const size_t LP = (size_t)a.waves * 64;
-    T* zr = static_cast<T*>(ta.zr);
-    T* lr = static_cast<T*>(ta.lr);
-    T* xr = static_cast<T*>(ta.xr);
-    const T inv_rho = a.inv_rho, rho = a.rho;
-    long long t = t0;
-    for (;;) {
-        const long long tn = t + 1;
-        // ---- decision of iteration tn - LAG
-        if (threadIdx.x == 0) {
-            long long spins = 0;
-            int bad = 0;
-            long long dseen = ld_agent(p.dec_iter);
-            int errseen = ld_agent(error);
-            while (dseen < tn - LAG && !bad && !errseen) {
-                __builtin_amdgcn_s_sleep(1);
-                dseen = ld_agent(p.dec_iter);
-                errseen = ld_agent(error);
-                if (++spins > p.spin_limit) bad = 1;
-            }
-            int stop = 0;
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);   // dec_stop is read after dec_iter
-            if (!bad && !errseen && tn - LAG > t0) stop = ld_agent(p.dec_stop) == tn - LAG;
-            if (bad) st_agent(error, (int)OPF_EHANG);
-            sh_flag = stop | ((errseen || bad) ? 2 : 0);
-        }
-        __syncthreads();
-        const int flag = sh_flag;
-        if (flag) {
-            if (flag == 1) {
-                // state of the end iteration ts into the iteration-parity buffers
-                const long long ts = tn - LAG;
-                const size_t rs = (size_t)(ts % kStateRing);
-                T* zo = (ts & 1) ? a.z1 : a.z0;
-                T* lo_ = (ts & 1) ? a.l1 : a.l0;
-                T* xo = (ts & 1) ? a.x1 : a.x0;
-                for (int j = b; j < ta.tiles; j += G) {
-                    const int d = (j * WPB + wv) * 64 + lane;
-                    const int g = a.var[d];
-                    if (g >= 0) {
-                        zo[d] = zr[rs * LP + d];
-                        lo_[d] = lr[rs * LP + d];
-                        if ((a.meta[d] >> 16) & 1) xo[g] = xr[rs * ta.n + g];
-                    }
-                }
-            }
-            break;
-        }
-        const unsigned tag = (unsigned)t;
-        const u64* pubr = p.pub + (size_t)(t & 1) * LP * W;
-        u64* pubw = p.pub + (size_t)(tn & 1) * LP * W;
-        const size_t rsrc = (size_t)(t % kStateRing), rdst = (size_t)(tn % kStateRing);
-        double s[5] = {0, 0, 0, 0, 0};
-        int bad = 0;
-        long long spins = 0;
-        for (int j = b; j < ta.tiles; j += G) {
-            const int w = j * WPB + wv;
-            const int d = w * 64 + lane;
-            const int g = a.var[d];
-            const bool live = g >= 0;
-            T acc = 0, zold = 0, lold = 0;
-            int meta = 0, cn = 1;
-            if (live) {
-                meta = a.meta[d];
-                const int cs = a.cstart[d];
-                cn = a.ccnt[d];
-                zold = zr[rsrc * LP + d];
-                lold = lr[rsrc * LP + d];
-                int cp[kCopyRegs];
-                u64 wd[kCopyRegs][W];
-                unsigned pending = 0;
-#pragma unroll
-                for (int k = 0; k < kCopyRegs; ++k) {
-                    cp[k] = k < cn ? a.clist[cs + k] : d;
-                    if (k < cn && cp[k] != d) {
-                        load_words<W>(pubr + (size_t)cp[k] * W, wd[k]);
-                        pending |= 1u << k;
-                    }
-                }
-                for (;;) {
-                    unsigned stale = 0;
-#pragma unroll
-                    for (int k = 0; k < kCopyRegs; ++k)
-                        if (((pending >> k) & 1u) && !tags_are<W>(wd[k], tag)) stale |= 1u << k;
-                    if (!stale || bad) break;
-                    __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-                    for (int k = 0; k < kCopyRegs; ++k)
-                        if ((stale >> k) & 1u) load_words<W>(pubr + (size_t)cp[k] * W, wd[k]);
-                    pending = stale;
-                    bad = wait_expired(++spins, error, p.spin_limit);
-                }
-#pragma unroll
-                for (int k = 0; k < kCopyRegs; ++k)
-                    if (k < cn) acc += (cp[k] == d) ? copy_term(zold, lold, inv_rho) : Tag<T>::unpack(wd[k]);
-                for (int k = kCopyRegs; k < cn; ++k) {
-                    const int e = a.clist[cs + k];
-                    u64 we[W];
-                    load_words<W>(pubr + (size_t)e * W, we);
-                    while (!tags_are<W>(we, tag) && !bad) {
-                        __builtin_amdgcn_s_sleep(1);
-                        load_words<W>(pubr + (size_t)e * W, we);
-                        bad = wait_expired(++spins, error, p.spin_limit);
-                    }
-                    acc += Tag<T>::unpack(we);
-                }
-            }
-            T xg = 0;
-            if (live) xg = consensus_value(acc, a.cost[d], inv_rho, cn, a.lo[d], a.hi[d]);
-            vsh[wv][lane] = live ? projection_input(xg, lold, inv_rho) : (T)0;
-            __builtin_amdgcn_wave_barrier();
-            if (live) {
-                const int2 wi = a.winfo[w];
-                const T z = project_row(a.F + (size_t)wi.y * 64, vsh[wv], meta & 255, lane, wi.x, a.bbar[d]);
-                const T ln = dual_step(lold, rho, xg, z);
-                u64 wout[W];
-                Tag<T>::pack(copy_term(z, ln, inv_rho), (unsigned)tn, wout);
-#pragma unroll
-                for (int h = 0; h < W; ++h) st_agent(pubw + (size_t)d * W + h, wout[h]);
-                zr[rdst * LP + d] = z;
-                lr[rdst * LP + d] = ln;
-                if ((meta >> 16) & 1) xr[rdst * ta.n + g] = xg;
-                const double xd = (double)xg, zd = (double)z;
-                s[0] += (xd - zd) * (xd - zd);
-                s[1] += (zd - (double)zold) * (zd - (double)zold);
-                s[2] += xd * xd;
-                s[3] += zd * zd;
-                s[4] += (double)ln * (double)ln;
-            }
-            // the next tile rewrites this wavefront's LDS row after every lane has read it
-            __builtin_amdgcn_wave_barrier();
-        }
-        if (__syncthreads_or(bad)) {
-            if (threadIdx.x == 0) st_agent(error, (int)OPF_EHANG);
-            break;
-        }
-        // ---- workgroup residual record of iteration tn (as the persistent kernel)
-#pragma unroll
-        for (int i = 0; i < 5; ++i) s[i] = wave_total(s[i]);
-        if (lane == 0)
-#pragma unroll
-            for (int i = 0; i < 5; ++i) red[wv][i] = s[i];
-        __syncthreads();
-        if (threadIdx.x < 5) {
-            const int i = threadIdx.x;
-            double bsum = 0.0;
-            for (int q = 0; q < WPB; ++q) bsum += red[q][i];
-            u64 two[2];
-            Tag<double>::pack(bsum, (unsigned)tn, two);
-            u64* rw = p.records + ((size_t)(tn % LAG) * kRec + 2 * i) * G + b;
-            st_agent(rw, two[0]);
-            st_agent(rw + G, two[1]);
-        }
-        t = tn;
-    }
-}
-
-// The state of the start iteration t0 into its ring position.
-template <typename T>
-__global__ void tiled_ring_init_kernel(IterArgs<T> a, TiledArgs ta) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long t0 = a.ctrl->iter;
-    const size_t LP = (size_t)a.waves * 64;
-    const size_t r = (size_t)(t0 % kStateRing);
-    T* zr = static_cast<T*>(ta.zr);
-    T* lr = static_cast<T*>(ta.lr);
-    T* xr = static_cast<T*>(ta.xr);
-    if (i < LP) {
-        zr[r * LP + i] = (t0 & 1) ? a.z1[i] : a.z0[i];
-        lr[r * LP + i] = (t0 & 1) ? a.l1[i] : a.l0[i];
-    }
-    if (i < (size_t)ta.n) xr[r * ta.n + i] = (t0 & 1) ? a.x1[i] : a.x0[i];
 }
 
 // Serving: the launch's workgroups are dealt to the resident solves by a work
@@ -882,6 +433,17 @@ __global__ void persistent_prepare_kernel(IterArgs<T> a, PersistArgs p, int G) {
     }
 }
 
+// The prepare kernel alone (the tiled schedule's launch starts with it).
+template <typename T>
+hipError_t launch_prepare(const IterArgs<T>& a, PersistArgs p, int G, hipStream_t st) {
+    const size_t LP = (size_t)a.waves * 64;
+    const int n = (int)std::max<size_t>(LP, (size_t)kDecisionLag * G * kRec);
+    hipLaunchKernelGGL((persistent_prepare_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, a, p, G);
+    return hipGetLastError();
+}
+template hipError_t launch_prepare<double>(const IterArgs<double>&, PersistArgs, int, hipStream_t);
+template hipError_t launch_prepare<float>(const IterArgs<float>&, PersistArgs, int, hipStream_t);
+
 template <typename T, bool ADAPT>
 hipError_t launch_persistent_as(const IterArgs<T>& a, PersistArgs p, int wpb, int G, size_t lds, hipStream_t st) {
     void* args[] = {(void*)&a, (void*)&p};
@@ -906,47 +468,6 @@ hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G
 }
 template hipError_t launch_persistent<double>(const IterArgs<double>&, PersistArgs, int, int, hipStream_t);
 template hipError_t launch_persistent<float>(const IterArgs<float>&, PersistArgs, int, int, hipStream_t);
-
-// Tiled schedule: G compute workgroups (plus the reducer) over ta.tiles tiles.
-template <typename T>
-hipError_t launch_tiled(const IterArgs<T>& a, PersistArgs p, const TiledArgs& ta, int wpb, int G, hipStream_t st) {
-    const size_t LP = (size_t)a.waves * 64;
-    const int n = (int)std::max<size_t>(LP, (size_t)kDecisionLag * G * kRec);
-    hipLaunchKernelGGL((persistent_prepare_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, a, p, G);
-    const size_t m = std::max<size_t>(LP, (size_t)ta.n);
-    hipLaunchKernelGGL((tiled_ring_init_kernel<T>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, a, ta);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    TiledArgs t = ta;
-    void* args[] = {(void*)&a, (void*)&p, (void*)&t};
-    switch (wpb) {
-        case 1: return hipLaunchCooperativeKernel((const void*)admm_tiled_kernel<T, 1>, dim3(G + 1), dim3(64), args, 0, st);
-        case 2: return hipLaunchCooperativeKernel((const void*)admm_tiled_kernel<T, 2>, dim3(G + 1), dim3(128), args, 0, st);
-        case 8: return hipLaunchCooperativeKernel((const void*)admm_tiled_kernel<T, 8>, dim3(G + 1), dim3(512), args, 0, st);
-        default: return hipLaunchCooperativeKernel((const void*)admm_tiled_kernel<T, 4>, dim3(G + 1), dim3(256), args, 0, st);
-    }
-}
-template hipError_t launch_tiled<double>(const IterArgs<double>&, PersistArgs, const TiledArgs&, int, int, hipStream_t);
-template hipError_t launch_tiled<float>(const IterArgs<float>&, PersistArgs, const TiledArgs&, int, int, hipStream_t);
-
-// Co-resident workgroups of the tiled kernel (0 on error).
-template <typename T>
-int tiled_capacity(int wpb) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    hipError_t e;
-    switch (wpb) {
-        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_kernel<T, 1>, 64, 0); break;
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_kernel<T, 2>, 128, 0); break;
-        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_kernel<T, 8>, 512, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_kernel<T, 4>, 256, 0); break;
-    }
-    if (e != hipSuccess) return 0;
-    return per * cus;
-}
-template int tiled_capacity<double>(int);
-template int tiled_capacity<float>(int);
 
 template <typename T, bool ADAPT>
 int persistent_capacity_as(int wpb, size_t lds_bytes) {
