@@ -131,7 +131,8 @@ struct opf_admm_handle {
     // persistent schedule
     int kernel = OPF_KERNEL_STEP;
     int capacity = 0;
-    int tiled_G = 0;               // tiled schedule: compute workgroups (tiles = lay.blocks)
+    int tiled_G = 0;               // tiled schedule: compute workgroups of the FP64 kernel (tiles = lay.blocks)
+    int tiled_G32 = 0;             // and of the FP32 kernel
     Work work;                     // the handle's own kernel scratch
     int xcd_remap = 1;
     int* error_host = nullptr;     // pinned
@@ -382,7 +383,7 @@ int run_phase_tiled(opf_admm_handle* h, PrecState<T>& s, long long max_iter, int
     ta.tiles = h->lay.blocks;
     ta.n = h->lay.n;
     HIPCHK(hipEventRecord(h->ev0, h->stream));
-    HIPCHK(launch_tiled<T>(a, p, ta, h->wpb, h->tiled_G, h->stream));
+    HIPCHK(launch_tiled<T>(a, p, ta, h->wpb, sizeof(T) == 4 ? h->tiled_G32 : h->tiled_G, h->stream));
     HIPCHK(hipEventRecord(h->ev1, h->stream));
     HIPCHK(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipMemcpyAsync(h->error_host, w.dev_error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -843,15 +844,20 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
                                               std::to_string(h->capacity)));
     // tiled schedule: as many co-resident workgroups as needed for an even
     // share of tiles (plus the reducer)
-    int tcap = tiled_capacity<double>(h->wpb);
-    if (opt.precision == OPF_PREC_MIXED) tcap = std::min(tcap, tiled_capacity<float>(h->wpb));
-    const bool tiled_ok = tcap >= 2 && opt.rho_every == 0;
+    // (per precision: the FP32 and FP64 kernels hold different numbers of workgroups)
+    const int tcap64 = tiled_capacity<double>(h->wpb);
+    const int tcap32 = opt.precision == OPF_PREC_MIXED ? tiled_capacity<float>(h->wpb) : tcap64;
+    const bool tiled_ok = std::min(tcap64, tcap32) >= 2 && opt.rho_every == 0;
     if (opt.tiled_workgroups < 0) return fail(set_err(h, OPF_EINVAL, "tiled_workgroups must be >= 0"));
-    if (tiled_ok) {
+    auto tiled_grid = [&](int tcap) {
         int gmax = std::min(tcap - 1, blocks);
         if (opt.tiled_workgroups > 0) gmax = std::min(gmax, opt.tiled_workgroups);
         const int per = (blocks + gmax - 1) / gmax;
-        h->tiled_G = (blocks + per - 1) / per;
+        return (blocks + per - 1) / per;
+    };
+    if (tiled_ok) {
+        h->tiled_G = tiled_grid(tcap64);
+        h->tiled_G32 = tiled_grid(tcap32);
     }
     if (opt.kernel == OPF_KERNEL_TILED && !tiled_ok)
         return fail(set_err(h, OPF_EINVAL, "the tiled schedule runs a fixed penalty on a device holding at least "
@@ -932,7 +938,8 @@ int opf_admm_get_info(const opf_admm_handle* h, opf_admm_info* info) {
     info->factor_bytes_fp64 = (int64_t)h->lay.F.size() * 8;
     info->device_bytes = (int64_t)h->device_bytes;
     info->setup_ms = h->setup_ms;
-    info->grid_blocks = h->kernel == OPF_KERNEL_TILED ? h->tiled_G : h->grid_blocks;
+    info->grid_blocks = h->kernel != OPF_KERNEL_TILED ? h->grid_blocks
+                        : (h->opt.precision == OPF_PREC_MIXED ? h->tiled_G32 : h->tiled_G);
     info->block_waves = h->wpb;
     info->kernel = h->kernel;
     info->persistent_capacity = h->capacity;
