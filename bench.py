@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--kernel", default="auto", choices=["auto", "step", "persistent", "tiled"])
     ap.add_argument("--block-waves", type=int, default=0)
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="schedule, workgroup shape and batch workgroup order chosen by the library's autotuner")
     ap.add_argument("--workgroup-order", type=int, default=0, choices=[0, 1],
                     help="persistent kernel: 0 = hardware workgroup order, 1 = XCD-contiguous packing ranges")
     ap.add_argument("--check-every", type=int, default=1024)
@@ -209,7 +211,7 @@ def single_instance(args, torch):
     flat = (inst.n, inst.c, inst.lb, inst.ub, inst.var_kind) + tuple(inst.flat())
     solver = Solver(*flat, rho=100.0, eps_rel=args.eps, precision=prec, check_every=args.check_every,
                     kernel=kern, block_waves=args.block_waves, workgroup_order=args.workgroup_order,
-                    stream=stream.cuda_stream)
+                    autotune=args.autotune, stream=stream.cuda_stream)
     info = solver.info()
     x = torch.zeros(inst.n, dtype=torch.float64, device=dev)
     fixed = args.fixed_iters or None
@@ -236,10 +238,11 @@ def single_instance(args, torch):
     bpi32 = algorithmic_bytes_per_iteration(info.sum_ns2, inst.L, inst.n, 4)
     bpi64 = algorithmic_bytes_per_iteration(info.sum_ns2, inst.L, inst.n, 8)
     # dominant kernel: the FP32 bulk in mixed mode, FP64 otherwise
+    bw = info.block_waves
     if prec == OPF_PREC_MIXED and it32 > 0:
-        dom_name, dom_bytes, dom_ms, dom_iters = "admm_persistent_kernel<float, 4>", bpi32, k32, it32
+        dom_name, dom_bytes, dom_ms, dom_iters = f"admm_persistent_kernel<float, {bw}>", bpi32, k32, it32
     else:
-        dom_name, dom_bytes, dom_ms, dom_iters = "admm_persistent_kernel<double, 4>", bpi64, k64, it64
+        dom_name, dom_bytes, dom_ms, dom_iters = f"admm_persistent_kernel<double, {bw}>", bpi64, k64, it64
     dom_launches = args.steps
     if info.kernel == 1:
         dom_name = dom_name.replace("persistent", "step")
@@ -249,7 +252,7 @@ def single_instance(args, torch):
     achieved = dom_bytes * dom_iters / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     tr = traffic_from_profiles(args.workload, args.precision)
     traffic = None
-    if tr is not None:
+    if tr is not None and tr.get("kernel", "").replace(", false", "") == dom_name:
         traffic = round(tr["bytes_per_iteration"] * dom_iters / max(dom_launches, 1))
     line = {
         "metric": METRIC,
@@ -302,7 +305,7 @@ def single_instance(args, torch):
     return line, inst
 
 
-def solve_leg(workload, precision, eps, torch, steps=1, fixed=None, **kw):
+def solve_leg(workload, precision, eps, torch, steps=1, fixed=None, warm=True, **kw):
     """One workload solved `steps` times (or `fixed` iterations timed), with
     the problem resident on the device: iterations, time, rate, accuracy and
     the algorithmic-bytes rate of its iteration kernel."""
@@ -315,7 +318,8 @@ def solve_leg(workload, precision, eps, torch, steps=1, fixed=None, **kw):
                precision=prec, check_every=1024, stream=stream.cuda_stream, max_iter=3_000_000, **kw)
     info = s.info()
     x = torch.zeros(inst.n, dtype=torch.float64, device="cuda")
-    s.solve(x=x, fixed_iters=fixed)                      # warm-up
+    if warm:
+        s.solve(x=x, fixed_iters=fixed)                  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     outs = [s.solve(x=x, fixed_iters=fixed) for _ in range(steps)]
@@ -336,11 +340,16 @@ def solve_leg(workload, precision, eps, torch, steps=1, fixed=None, **kw):
            "us_per_iteration": round(1e3 * kms / max(kit, 1), 3),
            "algorithmic_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
            "objective": r["objective"]}
+    if info.kernel == 3:
+        out["tiles_per_workgroup"] = "two in flight" if info.tiled_pair else "in turn"
     if kw:
         out["options"] = kw
         out["rho_final"] = r["rho_final"]
     if fixed is None:
-        out.update(accuracy(r["objective"], stored_reference(workload, eps)))
+        acc = accuracy(r["objective"], stored_reference(workload, eps))
+        if kw.get("rho_every") or kw.get("local_updates", 1) > 1:
+            acc.pop("objective_rel_err_vs_oracle", None)    # the stored solve is Algorithm 1 with fixed rho
+        out.update(acc)
     return out
 
 
@@ -357,7 +366,7 @@ def more_legs(args, torch):
     legs["21000bus_mixed_fixed4096"] = solve_leg("21000bus", "mixed", args.eps, torch, fixed=4096)
     legs["21000bus_fp64_fixed4096"] = solve_leg("21000bus", "fp64", args.eps, torch, fixed=4096)
     legs["21000bus_mixed_step_fixed4096"] = solve_leg("21000bus", "mixed", args.eps, torch, fixed=4096, kernel=1)
-    legs["21000bus_mixed"] = solve_leg("21000bus", "mixed", args.eps, torch)
+    legs["21000bus_mixed"] = solve_leg("21000bus", "mixed", args.eps, torch, warm=False)
     legs["8500bus_mixed_balanced"] = solve_leg("8500bus", "mixed", args.eps, torch, **BALANCE)
     return legs
 
@@ -372,9 +381,11 @@ def batch_leg(args, torch):
     B = scenario_rhs(inst, scenario_load_factors(f, K, seed=1000))
     st = torch.cuda.Stream()
     fixed = args.batch_fixed > 0
+    t_setup = time.perf_counter()
     s = BatchSolver(inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, *inst.flat(), b_scen=B, rho=100.0,
                     eps_rel=1e-12 if fixed else args.eps, max_iter=args.batch_fixed if fixed else 1_000_000,
-                    check_every=256, stream=st.cuda_stream)
+                    check_every=256, stream=st.cuda_stream, autotune=bool(args.autotune))
+    setup_s = time.perf_counter() - t_setup
     info = s.info()
     t0 = time.perf_counter()
     out = s.solve()
@@ -416,6 +427,9 @@ def batch_leg(args, torch):
                  "frac": round(tf / BF16_DENSE_PEAK_TFLOPS, 5),
                  "useful_fraction_of_issued": round(useful_flops * 6 / max(mfma_flops, 1), 4)},
         "precision": "bf16 three-term split products on MFMA, fp32 accumulate, fp32 state, fp64 residual sums",
+        "workgroup_order": {0: "hardware, wavefront-major", 1: "XCD-contiguous, wavefront-major",
+                            2: "hardware, chunk-major", 3: "XCD-contiguous, chunk-major"}.get(info.batch_order),
+        "setup_s_with_autotune": round(setup_s, 2),
         "zip_loads": zip_batch_timing(args, torch, K) if not fixed else None,
     }
 

@@ -125,8 +125,11 @@ typedef struct opf_admm_options {
                                OPF_EHANG (0 = default, several seconds) */
     int32_t split_terms;    /* batched path: bfloat16 terms per operand on MFMA, 2 or 3 (0 = 3) */
     int32_t autotune;       /* 1: with kernel AUTO and block_waves 0, time short runs of each
-                               schedule and workgroup shape on this problem and keep the fastest
-                               (decisions cached per problem shape for the process) */
+                               schedule and workgroup shape on this problem and keep the fastest;
+                               batched path: time each workgroup order of the step kernel
+                               (opf_admm_info.batch_order).  Decisions are cached per problem
+                               shape for the process and in the file named by OPF_ADMM_TUNE_CACHE
+                               (default $XDG_CACHE_HOME or $HOME/.cache, opf_admm/tune.txt) */
     int32_t workgroup_order; /* PERSISTENT: 0 = hardware order of workgroups (default; measured
                                faster), 1 = each XCD runs a contiguous range of the packing */
     int32_t setup_on_device; /* 1: row reduction and factors of every component run on the GPU
@@ -224,7 +227,12 @@ typedef struct opf_admm_info {
     int32_t persistent_capacity;   /* co-resident workgroups the device can hold */
     int32_t max_neighbours;    /* largest number of workgroups one workgroup waits on */
     int32_t factors_in_lds;    /* persistent schedule: bit 0 FP32, bit 1 FP64 factors held in LDS */
-    int32_t reserved[4];
+    int32_t batch_order;       /* batched path: workgroup order of the step kernel, bit 0 = each XCD runs
+                                  a contiguous range of the packing, bit 1 = 64-scenario-chunk-major */
+    int32_t tiled_pair;        /* TILED: 1 when the two-tile kernel runs (each workgroup keeps two tiles in
+                                  flight), 0 for the kernel that takes its tiles in turn (precision of the
+                                  bulk phase) */
+    int32_t reserved[2];
 } opf_admm_info;
 
 typedef struct opf_admm_handle opf_admm_handle;

@@ -93,7 +93,8 @@ class opf_admm_info(C.Structure):
                 ("sum_ns2", C.c_int64), ("factor_bytes_fp64", C.c_int64), ("device_bytes", C.c_int64),
                 ("setup_ms", C.c_double), ("grid_blocks", C.c_int32), ("block_waves", C.c_int32),
                 ("kernel", C.c_int32), ("persistent_capacity", C.c_int32), ("max_neighbours", C.c_int32),
-                ("factors_in_lds", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("factors_in_lds", C.c_int32), ("batch_order", C.c_int32), ("tiled_pair", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class opf_batch_result(C.Structure):
@@ -348,7 +349,7 @@ class BatchSolver:
 
     def __init__(self, n, c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx, b_scen, *, rho=100.0,
                  eps_rel=1e-4, max_iter=1_000_000, check_every=64, split_terms=3, stream=0, a_pos=None,
-                 a_scen=None):
+                 a_scen=None, autotune=False):
         keep = _keep(c, lb, ub, var_kind, comp_m, comp_n, A_vals, b_vals, idx)
         self.n = int(n)
         self.K = int(np.asarray(b_scen).shape[0])
@@ -358,6 +359,7 @@ class BatchSolver:
         o.max_iter = max_iter
         o.check_every = check_every
         o.split_terms = split_terms
+        o.autotune = int(bool(autotune))
         self.h = opf_admm_setup_batch(_problem(keep, n), b_scen, o, stream, a_pos=a_pos, a_scen=a_scen)
         _live.add(self)
 

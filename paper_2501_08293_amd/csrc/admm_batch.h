@@ -40,6 +40,7 @@ struct BatchArgs {
     BatchCtrl* ctrl;
     int W, Kp, K, n;
     float rho, inv_rho;
+    int order;              // workgroup order: bit 0 XCD-contiguous packing ranges, bit 1 chunk-major
 };
 
 struct BatchRedArgs {

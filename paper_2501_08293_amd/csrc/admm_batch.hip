@@ -58,11 +58,14 @@ __device__ __forceinline__ double wave_sum_b(double v) {
 }
 
 // grid W * Kp / 64, 256 threads: workgroup (wavefront w of the packing,
-// scenarios [kc, kc + 64)); each XCD runs a contiguous range of packing
-// positions, so the copies of a variable (in nearby wavefronts) and the four
-// scenario tiles of one factor tile meet in one L2.  The workgroups of the
-// scenario-varying wavefronts (the slowest, packed first) are dealt over all
-// XCDs and start first.  LDS 36.6 KiB: four workgroups per compute unit.
+// scenarios [kc, kc + 64)).  Order (tuned per problem, every order computes
+// the same values): bit 0 set, each XCD runs a contiguous range of packing
+// positions, so the copies of a variable (in nearby wavefronts) and the
+// scenario tiles of one factor tile meet in one L2; bit 1 set, positions run
+// scenario-chunk-major (all wavefronts of one 64-scenario chunk, then the
+// next) instead of wavefront-major.  The workgroups of the scenario-varying
+// wavefronts (the slowest, packed first) are dealt over all XCDs and start
+// first.  LDS 36.6 KiB: four workgroups per compute unit.
 __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     if (a.ctrl->stop) return;
     const long long t = a.ctrl->iter + 1;
@@ -80,7 +83,13 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int KB = a.Kp >> 6;
     const int nvb = a.vary_waves * KB, bx = (int)blockIdx.x;
-    const int pos = bx < nvb ? bx : nvb + logical_block(bx - nvb, (int)gridDim.x - nvb, 1);
+    const int rest = (int)gridDim.x - nvb;
+    int pos = bx < nvb ? bx : nvb + logical_block(bx - nvb, rest, a.order & 1);
+    if ((a.order & 2) && pos >= nvb) {
+        // chunk-major over the wavefronts after the scenario-varying ones
+        const int q = pos - nvb, wr = rest / KB;
+        pos = nvb + (q % wr) * KB + q / wr;
+    }
     const int w = pos / KB;
     const int kc = (pos - w * KB) * 64;
 

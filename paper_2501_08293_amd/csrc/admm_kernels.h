@@ -196,6 +196,7 @@ struct TiledArgs {
     void* xr;                   // [kStateRing][n] global variables (written by owner slots)
     int tiles;                  // workgroup tiles of the packing (block_waves wavefronts each)
     int n;
+    int pair;                   // 1: at most two tiles per workgroup, both in flight (admm_tiled_pair_kernel)
 };
 
 // Iterations between a residual reduction and the moment workgroups act on

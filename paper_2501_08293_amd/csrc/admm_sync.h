@@ -79,7 +79,7 @@ __device__ __forceinline__ int wait_expired(long long spins, int* error, long lo
 }
 
 constexpr int kCopyRegs = 8;
-constexpr int kBatch = 3;      // workgroups whose records a reducer thread loads at once
+constexpr int kBatch = 3;      // workgroups whose records a reducer thread loads at once (default)
 constexpr int kRec = 10;       // words of one residual record (5 doubles, two tagged halves each)
 
 // Everything one solve's persistent loop touches, for the single-instance
@@ -122,8 +122,9 @@ struct InstanceView {
 // Reducer workgroup of one solve: stop decisions of every iteration.  A
 // decision ends the launch for the solve when the test holds, on a NaN/Inf,
 // at max_iter, or after `chunk` iterations of this launch (a pause: the solve
-// continues in the next launch from the state written at the pause).
-template <typename T, int NT, bool ADAPT>
+// continues in the next launch from the state written at the pause).  BATCH:
+// workgroups whose records one thread loads at once (fewer: fewer registers).
+template <typename T, int NT, bool ADAPT, int BATCH = kBatch>
 __device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int* error, long long spin_limit) {
     __shared__ double rred[NT / 64][5];
     __shared__ int rstop;
@@ -142,11 +143,11 @@ __device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int*
         double acc5[5] = {0, 0, 0, 0, 0};
         int bad = 0;
         long long spins = 0;
-        for (int q0 = threadIdx.x; q0 < G; q0 += kBatch * NT) {
-            u64 wd[kBatch][kRec];
+        for (int q0 = threadIdx.x; q0 < G; q0 += BATCH * NT) {
+            u64 wd[BATCH][kRec];
             unsigned pending = 0;
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
+            for (int k = 0; k < BATCH; ++k) {
                 const int q = q0 + k * NT;
                 if (q < G) {
 #pragma unroll
@@ -157,12 +158,12 @@ __device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int*
             for (;;) {
                 unsigned stale = 0;
 #pragma unroll
-                for (int k = 0; k < kBatch; ++k)
+                for (int k = 0; k < BATCH; ++k)
                     if (((pending >> k) & 1u) && !tags_are<kRec>(wd[k], tag)) stale |= 1u << k;
                 if (!stale || bad) break;
                 __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-                for (int k = 0; k < kBatch; ++k)
+                for (int k = 0; k < BATCH; ++k)
                     if ((stale >> k) & 1u)
 #pragma unroll
                         for (int h = 0; h < kRec; ++h) wd[k][h] = ld_agent(rec + (size_t)h * G + q0 + k * NT);
@@ -170,7 +171,7 @@ __device__ void reducer_loop(const InstanceView<T>& v, int G, long long t0, int*
                 bad = wait_expired(++spins, error, spin_limit);
             }
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k)
+            for (int k = 0; k < BATCH; ++k)
                 if (q0 + k * NT < G)
 #pragma unroll
                     for (int i = 0; i < 5; ++i) {

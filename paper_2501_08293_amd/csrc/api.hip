@@ -15,6 +15,7 @@
 #include "../../include/opf_admm.h"
 #include "admm_kernels.h"
 #include "setup_device.h"
+#include "tune_cache.h"
 #include "opf_layout.h"
 
 namespace opf {
@@ -32,7 +33,7 @@ hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G
 template <typename T> int persistent_capacity(int wpb, size_t lds_bytes, int adapt);
 template <typename T>
 hipError_t launch_tiled(const IterArgs<T>& a, PersistArgs p, const TiledArgs& ta, int wpb, int G, hipStream_t st);
-template <typename T> int tiled_capacity(int wpb);
+template <typename T> int tiled_capacity(int wpb, int pair);
 template <typename T>
 hipError_t launch_output(const T* z0, const T* z1, const T* l0, const T* l1, const T* x0, const T* x1,
                          const int* user_slot, int LP, int n, const double* c, double* xo, double* zo,
@@ -133,6 +134,7 @@ struct opf_admm_handle {
     int capacity = 0;
     int tiled_G = 0;               // tiled schedule: compute workgroups of the FP64 kernel (tiles = lay.blocks)
     int tiled_G32 = 0;             // and of the FP32 kernel
+    int tiled_pair64 = 0, tiled_pair32 = 0;   // the two-tile kernel runs (per precision)
     Work work;                     // the handle's own kernel scratch
     int xcd_remap = 1;
     int* error_host = nullptr;     // pinned
@@ -382,6 +384,7 @@ int run_phase_tiled(opf_admm_handle* h, PrecState<T>& s, long long max_iter, int
     ta.xr = s.xr;
     ta.tiles = h->lay.blocks;
     ta.n = h->lay.n;
+    ta.pair = sizeof(T) == 4 ? h->tiled_pair32 : h->tiled_pair64;
     HIPCHK(hipEventRecord(h->ev0, h->stream));
     HIPCHK(launch_tiled<T>(a, p, ta, h->wpb, sizeof(T) == 4 ? h->tiled_G32 : h->tiled_G, h->stream));
     HIPCHK(hipEventRecord(h->ev1, h->stream));
@@ -697,10 +700,13 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
             auto it = g_tune.find(key);
             if (it != g_tune.end()) choice = it->second;
         }
+        std::vector<int> cached;
+        if (!choice.first && tune_cache_get("single/" + key, cached) && cached.size() == 2)
+            choice = {cached[0], cached[1]};
         if (!choice.first) {
             double best = 1e300;
             const int cands[][2] = {{OPF_KERNEL_PERSISTENT, 2}, {OPF_KERNEL_PERSISTENT, 4}, {OPF_KERNEL_PERSISTENT, 8},
-                                    {OPF_KERNEL_STEP, 4}, {OPF_KERNEL_STEP, 8}};
+                                    {OPF_KERNEL_TILED, 4}, {OPF_KERNEL_STEP, 4}, {OPF_KERNEL_STEP, 8}};
             for (const auto& c : cands) {
                 opf_admm_options t = opt;
                 t.autotune = 0;
@@ -720,6 +726,7 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
                 if (ms < best) { best = ms; choice = {c[0], c[1]}; }
             }
             if (!choice.first) choice = {OPF_KERNEL_AUTO, 4};
+            else tune_cache_put("single/" + key, {choice.first, choice.second});
             std::lock_guard<std::mutex> lk(g_tune_mu);
             g_tune[key] = choice;
         }
@@ -844,20 +851,31 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
                                               std::to_string(h->capacity)));
     // tiled schedule: as many co-resident workgroups as needed for an even
     // share of tiles (plus the reducer)
-    // (per precision: the FP32 and FP64 kernels hold different numbers of workgroups)
-    const int tcap64 = tiled_capacity<double>(h->wpb);
-    const int tcap32 = opt.precision == OPF_PREC_MIXED ? tiled_capacity<float>(h->wpb) : tcap64;
-    const bool tiled_ok = std::min(tcap64, tcap32) >= 2 && opt.rho_every == 0;
+    // (per precision: the FP32 and FP64 kernels hold different numbers of
+    // workgroups).  When every workgroup can take at most two tiles, the
+    // two-tile kernel (both tiles in flight) runs with ceil(tiles / 2)
+    // workgroups; otherwise the loop kernel with an even share each.
     if (opt.tiled_workgroups < 0) return fail(set_err(h, OPF_EINVAL, "tiled_workgroups must be >= 0"));
-    auto tiled_grid = [&](int tcap) {
-        int gmax = std::min(tcap - 1, blocks);
+    auto tiled_grid = [&](int cap_loop, int cap_pair, int* pair) {
+        int gmax = std::min(cap_loop - 1, blocks);
         if (opt.tiled_workgroups > 0) gmax = std::min(gmax, opt.tiled_workgroups);
+        const int gpair = (blocks + 1) / 2;
+        if (blocks >= 2 && gpair + 1 <= cap_pair && (opt.tiled_workgroups == 0 || opt.tiled_workgroups >= gpair)) {
+            *pair = 1;
+            return gpair;
+        }
+        *pair = 0;
         const int per = (blocks + gmax - 1) / gmax;
         return (blocks + per - 1) / per;
     };
+    const int tcap64 = tiled_capacity<double>(h->wpb, 0);
+    const int tcap32 = opt.precision == OPF_PREC_MIXED ? tiled_capacity<float>(h->wpb, 0) : tcap64;
+    const int pcap64 = tiled_capacity<double>(h->wpb, 1);
+    const int pcap32 = opt.precision == OPF_PREC_MIXED ? tiled_capacity<float>(h->wpb, 1) : pcap64;
+    const bool tiled_ok = std::min(tcap64, tcap32) >= 2 && opt.rho_every == 0;
     if (tiled_ok) {
-        h->tiled_G = tiled_grid(tcap64);
-        h->tiled_G32 = tiled_grid(tcap32);
+        h->tiled_G = tiled_grid(tcap64, pcap64, &h->tiled_pair64);
+        h->tiled_G32 = tiled_grid(tcap32, pcap32, &h->tiled_pair32);
     }
     if (opt.kernel == OPF_KERNEL_TILED && !tiled_ok)
         return fail(set_err(h, OPF_EINVAL, "the tiled schedule runs a fixed penalty on a device holding at least "
@@ -945,6 +963,8 @@ int opf_admm_get_info(const opf_admm_handle* h, opf_admm_info* info) {
     info->persistent_capacity = h->capacity;
     info->max_neighbours = h->lay.max_nbrs;
     info->factors_in_lds = h->lds32 | (h->lds64 << 1);
+    if (h->kernel == OPF_KERNEL_TILED)
+        info->tiled_pair = h->opt.precision == OPF_PREC_MIXED ? h->tiled_pair32 : h->tiled_pair64;
     return 0;
 }
 

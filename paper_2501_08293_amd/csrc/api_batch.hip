@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/opf_admm.h"
+#include "tune_cache.h"
 #include "admm_batch.h"
 #include "admm_kernels.h"
 #include "opf_layout.h"
@@ -56,6 +57,7 @@ struct opf_admm_batch {
     double* xout = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_k = 0;
+    int order = 1;                  // workgroup order of the step kernel (BatchArgs::order)
 };
 
 namespace {
@@ -105,6 +107,7 @@ void args_of(opf_admm_batch* h, BatchArgs& a, BatchRedArgs& r) {
     a.part = h->part; a.ctrl = h->ctrl;
     a.W = h->lay.waves; a.Kp = h->Kp; a.K = h->K; a.n = h->lay.n;
     a.rho = (float)h->opt.rho; a.inv_rho = (float)(1.0 / h->opt.rho);
+    a.order = h->order;
     r.part = h->part; r.ctrl = h->ctrl; r.state = h->state; r.iters = h->iters; r.res = h->res;
     r.objective = h->objective; r.xout = h->xout; r.x0 = h->x[0]; r.x1 = h->x[1]; r.c = h->c;
     r.W = h->lay.waves; r.Kp = h->Kp; r.K = h->K; r.n = h->lay.n;
@@ -112,6 +115,54 @@ void args_of(opf_admm_batch* h, BatchArgs& a, BatchRedArgs& r) {
 }
 
 }  // namespace
+
+// Autotuner of the batched iteration: each workgroup order of the step
+// kernel (XCD-contiguous or hardware order, wavefront- or chunk-major) is
+// timed over 64 iterations after 8 untimed ones, on this problem, and the
+// fastest kept; decisions are cached per problem shape (tune_cache.h).  All
+// orders compute the same values.
+int tune_batch(opf_admm_batch* h) {
+    const std::string key = "batch/" + std::to_string(h->lay.waves) + "/" + std::to_string(h->Kp) + "/" +
+                            std::to_string(h->terms) + "/" + std::to_string(h->vary_waves) + "/" +
+                            std::to_string(h->lay.L) + "/" + std::to_string(h->lay.sum_ns2);
+    std::vector<int> got;
+    if (tune_cache_get(key, got) && got.size() == 1) {
+        h->order = got[0];
+        return 0;
+    }
+    struct Events {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    BHIP(hipEventCreate(&ev.e0));
+    BHIP(hipEventCreate(&ev.e1));
+    float best = 1e30f;
+    int bo = 1;
+    for (int order : {1, 0, 3, 2}) {
+        h->order = order;
+        BatchArgs a;
+        BatchRedArgs rr;
+        args_of(h, a, rr);
+        BHIP(launch_batch_init(h->z0, h->z[0], h->l[0], h->LP, h->Kp, h->ctrl, h->state, h->K, 1LL << 40, h->stream));
+        for (int i = 0; i < 8; ++i) BHIP(launch_batch_iteration(a, rr, h->stream));
+        BHIP(hipEventRecord(ev.e0, h->stream));
+        for (int i = 0; i < 64; ++i) BHIP(launch_batch_iteration(a, rr, h->stream));
+        BHIP(hipEventRecord(ev.e1, h->stream));
+        BHIP(hipStreamSynchronize(h->stream));
+        float ms = 0.0f;
+        BHIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+        if (ms < best) {
+            best = ms;
+            bo = order;
+        }
+    }
+    h->order = bo;
+    tune_cache_put(key, {bo});
+    return 0;
+}
 
 extern "C" {
 
@@ -288,6 +339,7 @@ int opf_admm_setup_batch_ex(const opf_problem* p, const double* b_scen, int32_t 
     if ((rc = balloc(h, &h->objective, K))) return fail(rc);
     if ((rc = balloc(h, &h->xout, (size_t)K * L.n))) return fail(rc);
     if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(berr(h, OPF_EHIP, "sync"));
+    if (opt.autotune && (rc = tune_batch(h))) return fail(rc);
     h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = h;
     return OPF_OK;
@@ -373,9 +425,10 @@ int opf_admm_batch_info(const opf_admm_batch* h, opf_admm_info* info) {
     info->factor_bytes_fp64 = (int64_t)h->lay.F.size() * 8;
     info->device_bytes = (int64_t)h->device_bytes;
     info->setup_ms = h->setup_ms;
-    info->grid_blocks = h->lay.waves;
+    info->grid_blocks = h->lay.waves * (h->Kp / 64);
     info->block_waves = 4;
     info->kernel = OPF_KERNEL_STEP;
+    info->batch_order = h->order;
     return 0;
 }
 

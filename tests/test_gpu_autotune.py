@@ -1,0 +1,85 @@
+"""The autotuners: every workgroup order of the batched step kernel gives the
+same values bit for bit; the batch and single-instance tuners pick a valid
+configuration, write it to the decision cache file and read it back."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from opfgen import build_instance, by_name, scenario_load_factors, scenario_rhs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _batch(inst, B, **kw):
+    from paper_2501_08293_amd import BatchSolver
+    return BatchSolver(inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, *inst.flat(), b_scen=B, **kw)
+
+
+def test_batch_orders_and_autotune_cache(tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("OPF_ADMM_TUNE_CACHE", str(cache))
+    f = by_name("123bus", 0)
+    inst = build_instance(f)
+    B = scenario_rhs(inst, scenario_load_factors(f, 130, seed=21))
+    _say("[gpu] batch autotune 123bus K=130 (three 64-scenario chunks)")
+    s = _batch(inst, B, rho=100.0, eps_rel=1e-12, max_iter=60, check_every=20, autotune=True)
+    order = s.info().batch_order
+    tuned = s.solve()
+    s.close()
+    assert order in (0, 1, 2, 3)
+    assert cache.exists() and "batch/" in cache.read_text()
+    # a second set-up reads the decision back from the file
+    s = _batch(inst, B, rho=100.0, eps_rel=1e-12, max_iter=60, check_every=20, autotune=True)
+    assert s.info().batch_order == order
+    s.close()
+    # every order computes the same values: the default order (no tuning) gives the tuned run's bits
+    s = _batch(inst, B, rho=100.0, eps_rel=1e-12, max_iter=60, check_every=20)
+    ref = s.solve()
+    s.close()
+    assert np.array_equal(tuned["x"], ref["x"]) and np.array_equal(tuned["iterations"], ref["iterations"])
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_each_batch_order_gives_the_same_bits(tmp_path, monkeypatch, order):
+    # a cache file holding the order forces it
+    f = by_name("13bus", 0)
+    inst = build_instance(f)
+    B = scenario_rhs(inst, scenario_load_factors(f, 70, seed=5))
+    s = _batch(inst, B, rho=100.0, eps_rel=1e-12, max_iter=40, check_every=8)
+    ref = s.solve()
+    info = s.info()
+    s.close()
+    key = f"batch/{info.waves}/128/3/0/{info.L}/{info.sum_ns2}"
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{key}\t{order}\n")
+    monkeypatch.setenv("OPF_ADMM_TUNE_CACHE", str(cache))
+    _say(f"[gpu] batch order {order} vs default, 13bus K=70")
+    s = _batch(inst, B, rho=100.0, eps_rel=1e-12, max_iter=40, check_every=8, autotune=True)
+    assert s.info().batch_order == order
+    out = s.solve()
+    s.close()
+    assert np.array_equal(out["x"], ref["x"])
+
+
+def test_single_instance_autotune_cache(tmp_path, monkeypatch):
+    from paper_2501_08293_amd import Solver
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("OPF_ADMM_TUNE_CACHE", str(cache))
+    inst = build_instance(by_name("13bus-zip", 0))
+    _say("[gpu] single-instance autotune writes its decision to the cache file")
+    s = Solver(inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, *inst.flat(), rho=100.0, eps_rel=1e-4,
+               autotune=True)
+    info = s.info()
+    s.close()
+    txt = cache.read_text()
+    assert "single/" in txt
+    line = [l for l in txt.splitlines() if l.startswith("single/")][-1]
+    k, bw = (int(v) for v in line.split("\t")[1].split())
+    assert (info.kernel, info.block_waves) == (k, bw)

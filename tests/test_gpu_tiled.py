@@ -41,6 +41,17 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b)))))
 
 
+def _tiles(info):
+    return -(-info.waves // info.block_waves)
+
+
+def _expect_pair(info, G):
+    """The two-tile kernel runs when no workgroup would take more than two
+    tiles (small problems: it fits the device)."""
+    tiles = _tiles(info)
+    return int(tiles >= 2 and (G == 0 or G >= -(-tiles // 2)))
+
+
 @pytest.mark.parametrize("name,bw,G", [("13bus", 1, 1), ("123bus", 1, 0), ("123bus", 1, 3), ("123bus", 2, 2),
                                        ("13bus-zip", 1, 1)])
 @pytest.mark.parametrize("t", [1, 3, 10, 100])
@@ -53,6 +64,7 @@ def test_tiled_iterates_match_oracle_fp64(name, bw, G, t):
     out = s.solve(fixed_iters=t)
     s.close()
     assert info.kernel == TILED
+    assert info.tiled_pair == _expect_pair(info, G)
     assert out["iterations"] == t
     assert _rel(out["x"], ref.x) < 1e-9
     assert _rel(out["z"], ref.z) < 1e-9
@@ -115,9 +127,52 @@ def test_tiled_21000bus_equals_step_schedule(prec):
     b = s.solve(fixed_iters=50)
     s.close()
     assert info.kernel == TILED
-    _say(f"  tiled: {info.grid_blocks} workgroups")
+    _say(f"  tiled: {info.grid_blocks} workgroups, two-tile kernel {info.tiled_pair}")
+    if prec == "mixed":
+        assert info.tiled_pair == 1 and info.grid_blocks == -(-_tiles(info) // 2)
     for f in ("x", "z", "lam"):
         assert np.array_equal(a[f], b[f]), f
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_tiled_pair_odd_tile_count(prec):
+    """The two-tile kernel on an odd number of tiles (the last workgroup
+    holds one): iterates at t = 10 and 200 against the oracle (FP64, 1e-9) and
+    equal to the step schedule's bit for bit."""
+    from paper_2501_08293_amd import OPF_PREC_FP64, OPF_PREC_MIXED
+    p = OPF_PREC_FP64 if prec == "fp64" else OPF_PREC_MIXED
+    chosen = None
+    for name in ("123bus", "13bus", "13bus-zip"):
+        for bw in (1, 2, 4):
+            s = _solver(_inst(name), rho=RHO, eps_rel=1e-4, kernel=TILED, block_waves=bw, precision=p)
+            info = s.info()
+            s.close()
+            if _tiles(info) % 2 == 1 and _tiles(info) >= 3:
+                chosen = (name, bw)
+                break
+        if chosen:
+            break
+    if chosen is None:
+        pytest.skip("no test feeder packs into an odd number of at least three tiles")
+    name, bw = chosen
+    inst = _inst(name)
+    for t in (10, 200):
+        _say(f"[gpu] two-tile kernel, odd tile count: {name} block_waves={bw} t={t} ({prec})")
+        s = _solver(inst, rho=RHO, eps_rel=1e-4, kernel=TILED, block_waves=bw, precision=p)
+        info = s.info()
+        a = s.solve(fixed_iters=t)
+        s.close()
+        assert info.tiled_pair == 1 and info.grid_blocks == (_tiles(info) + 1) // 2
+        s = _solver(inst, rho=RHO, eps_rel=1e-4, kernel=STEP, block_waves=bw, precision=p)
+        b = s.solve(fixed_iters=t)
+        s.close()
+        for f in ("x", "z", "lam"):
+            assert np.array_equal(a[f], b[f]), (t, f)
+        if prec == "fp64":
+            ref = admm.solve(admm.setup(inst), rho=RHO, eps_rel=1e-4, fixed_iters=t)
+            assert _rel(a["x"], ref.x) < 1e-9
+            assert _rel(a["z"], ref.z) < 1e-9
+            assert _rel(a["lam"], ref.lam) < 1e-9
 
 
 def test_tiled_forced_wait_timeout_reports_ehang():
