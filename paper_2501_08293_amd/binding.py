@@ -147,10 +147,6 @@ def close_all() -> None:
 atexit.register(close_all)
 
 
-def _finalizing() -> bool:
-    return sys.is_finalizing()
-
-
 def load(path: str = LIB_PATH):
     """Loads the HIP library (raises if it is missing)."""
     global _lib
@@ -368,8 +364,10 @@ class BatchSolver:
             opf_admm_destroy_batch(self.h)
             self.h = None
 
-    def __del__(self):
-        if _finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check callable after module teardown
+        # has cleared this module's globals
+        if getattr(self, "h", None) is None or _finalizing():
             return
         try:
             self.close()
@@ -468,8 +466,10 @@ class Solver:
             opf_admm_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if _finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check callable after module teardown
+        # has cleared this module's globals
+        if getattr(self, "h", None) is None or _finalizing():
             return
         try:
             self.close()
@@ -614,8 +614,10 @@ class Server:
             load().opf_server_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if _finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check callable after module teardown
+        # has cleared this module's globals
+        if getattr(self, "h", None) is None or _finalizing():
             return
         try:
             self.close()

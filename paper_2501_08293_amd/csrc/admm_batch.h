@@ -7,6 +7,9 @@
 
 namespace opf {
 
+constexpr int kBatchKernelRev = 2;   // revision of the step kernel (tuning decisions are kept per revision)
+constexpr int kBatchCopies = 6;    // copies per variable gathered from the slot record (more: from the copy list)
+
 // ---- batched same-topology scenarios (see admm_batch.hip)
 struct BatchCtrl {
     long long iter;         // completed iterations
@@ -24,18 +27,16 @@ struct BatchArgs {
     const float* Fv;        // [varying wave][fv_cols][64][Kp] per-scenario factors (FP32)
     int fv_cols;
     int vary_waves;         // the varying wavefronts lie in [0, vary_waves) of the packing (0: none)
-    const int* var;
+    const int4* sdesc;      // [LP] per slot: variable (-1: padding), copies, first copy in clist, owner
+    const float4* sval;     // [LP] per slot: cost, lower bound, upper bound, 0
+    const int4* scopy;      // [LP][2] per slot: its variable's first kBatchCopies copies (then the slot itself)
     const int* meta;        // base lane | n_s << 8 | owner << 16
-    const int* cstart;
-    const int* ccnt;
     const int* clist;
-    const float* lo;
-    const float* hi;
-    const float* cost;
-    const float* bbar;      // [LP][Kp]
-    float* z0; float* z1;   // [LP][Kp] ping-pong
+    // scenario state, chunk-major: 64-scenario chunk c of slot d at (c LP + d) 64
+    const float* bbar;      // [Kp / 64][LP][64]
+    float* z0; float* z1;   // [Kp / 64][LP][64] ping-pong
     float* l0; float* l1;
-    float* x0; float* x1;   // [n][Kp]
+    float* x0; float* x1;   // [Kp / 64][n][64]
     double* part;           // [5][Kp][W] per-wavefront residual partials
     BatchCtrl* ctrl;
     int W, Kp, K, n;

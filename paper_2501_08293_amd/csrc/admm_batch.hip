@@ -34,7 +34,6 @@ namespace opf {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kBatchCopies = 6;    // copies per variable gathered from registers (more: from memory)
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
@@ -51,6 +50,16 @@ __device__ __forceinline__ bf16x8 as_bf16x8(const uint16_t (&h)[8]) {
     return r;
 }
 
+// Element at a 32-bit byte offset from a base address that is the same for
+// the whole workgroup (one base register pair instead of a 64-bit address per
+// load in flight).
+__device__ __forceinline__ float ld32(const float* base, uint32_t off) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + off);
+}
+__device__ __forceinline__ void st32(float* base, uint32_t off, float v) {
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
 __device__ __forceinline__ double wave_sum_b(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -65,20 +74,20 @@ __device__ __forceinline__ double wave_sum_b(double v) {
 // scenario-chunk-major (all wavefronts of one 64-scenario chunk, then the
 // next) instead of wavefront-major.  The workgroups of the scenario-varying
 // wavefronts (the slowest, packed first) are dealt over all XCDs and start
-// first.  LDS 36.6 KiB: four workgroups per compute unit.
+// first.
+//
+// Phases 1 and 3 share one layout (wave wv: slots 16 wv .. 16 wv + 15, lane:
+// scenario), so x and the slot's own lambda, loaded in phase 1, stay in
+// registers until phase 3; the product Z comes back from the matrix cores
+// through the V tile's LDS.  LDS 30 KiB.
 __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     if (a.ctrl->stop) return;
     const long long t = a.ctrl->iter + 1;
     const bool odd = (t & 1) != 0;
-    const float* zp = odd ? a.z0 : a.z1;
-    const float* lp = odd ? a.l0 : a.l1;
-    float* zq = odd ? a.z1 : a.z0;
-    float* lq = odd ? a.l1 : a.l0;
-    float* xq = odd ? a.x1 : a.x0;
     const size_t Kp = (size_t)a.Kp;
 
-    __shared__ float xs[64][65];      // [slot][scenario]
-    __shared__ __align__(16) float vs[64][65];
+    __shared__ __align__(16) float vs[64][65];   // V = B x + lambda / rho, then Z = F_w V   [slot][scenario]
+    __shared__ double red[4][5][64];              // residual partials per wave and scenario
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int KB = a.Kp >> 6;
@@ -91,74 +100,84 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
         pos = nvb + (q % wr) * KB + q / wr;
     }
     const int w = pos / KB;
-    const int kc = (pos - w * KB) * 64;
+    const int chunk = pos - w * KB, kc = chunk * 64;
+    // state of this 64-scenario chunk: [slot][64] (x: [variable][64])
+    const size_t sb = (size_t)chunk * a.W * 64 * 64, xb = (size_t)chunk * a.n * 64;
+    const float* zp = (odd ? a.z0 : a.z1) + sb;
+    const float* lp = (odd ? a.l0 : a.l1) + sb;
+    float* zq = (odd ? a.z1 : a.z0) + sb;
+    float* lq = (odd ? a.l1 : a.l0) + sb;
+    float* xq = (odd ? a.x1 : a.x0) + xb;
+    const float* bbar = a.bbar + sb;
 
-    // ---- slot descriptors of this wavefront staged in LDS (one load per thread)
+    // ---- slot descriptors of this wavefront staged in LDS: one 16-byte
+    // record per slot and its first copies, loaded side by side
     __shared__ int s_var[64], s_cn[64], s_cs[64], s_owner[64];
     __shared__ float s_cost[64], s_lo[64], s_hi[64];
     __shared__ int s_copy[64][kBatchCopies];
     if (tid < 64) {
         const int d = w * 64 + tid;
-        const int g = a.var[d];
-        s_var[tid] = g;
-        int cn = 0, cs = 0;
-        if (g >= 0) {
-            cn = a.ccnt[d];
-            cs = a.cstart[d];
-            s_owner[tid] = (a.meta[d] >> 16) & 1;
-            s_cost[tid] = a.cost[d] * a.inv_rho;
-            s_lo[tid] = a.lo[d];
-            s_hi[tid] = a.hi[d];
-        }
-        s_cn[tid] = cn;
-        s_cs[tid] = cs;
+        const int4 sd = a.sdesc[d];
+        const float4 sv = a.sval[d];
+        s_var[tid] = sd.x;
+        s_cn[tid] = sd.y;
+        s_cs[tid] = sd.z;
+        s_owner[tid] = sd.w;
+        s_cost[tid] = sv.x * a.inv_rho;
+        s_lo[tid] = sv.y;
+        s_hi[tid] = sv.z;
+    } else if (tid < 128) {
+        const int r = tid - 64;
+        const int4 c0 = a.scopy[(size_t)(w * 64 + r) * 2];
+        const int4 c1 = a.scopy[(size_t)(w * 64 + r) * 2 + 1];
+        const int c[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
 #pragma unroll
-        for (int q = 0; q < kBatchCopies; ++q) s_copy[tid][q] = q < cn ? a.clist[cs + q] : d;
+        for (int q = 0; q < kBatchCopies; ++q) s_copy[r][q] = c[q];
     }
     __syncthreads();
 
     // ---- phase 1: consensus average and projection input, 16 slots per
     // wave in groups of four whose gathers are in flight together
-    {
-        const size_t k = (size_t)(kc + lane);
+    const uint32_t lane4 = 4u * lane;
+    float xr[16], lr[16];
 #pragma unroll
-        for (int r0 = 0; r0 < 16; r0 += 4) {
-            float zz[4][kBatchCopies], ll[4][kBatchCopies], lown[4];
+    for (int r0 = 0; r0 < 16; r0 += 4) {
+        float zz[4][kBatchCopies], ll[4][kBatchCopies];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int r = wv * 16 + r0 + j;
-                const int cn = s_cn[r];
+        for (int j = 0; j < 4; ++j) {
+            const int r = wv * 16 + r0 + j;
+            const int cn = s_cn[r];
+            const uint32_t dk = (uint32_t)(w * 64 + r) * 256u + lane4;
 #pragma unroll
-                for (int q = 0; q < kBatchCopies; ++q) {
-                    const size_t e = (size_t)s_copy[r][q];
-                    zz[j][q] = q < cn ? zp[e * Kp + k] : 0.0f;
-                    ll[j][q] = q < cn ? lp[e * Kp + k] : 0.0f;
-                }
-                lown[j] = s_var[r] >= 0 ? lp[(size_t)(w * 64 + r) * Kp + k] : 0.0f;
+            for (int q = 0; q < kBatchCopies; ++q) {
+                const uint32_t e = (uint32_t)s_copy[r][q] * 256u + lane4;
+                zz[j][q] = q < cn ? ld32(zp, e) : 0.0f;
+                ll[j][q] = q < cn ? ld32(lp, e) : 0.0f;
             }
+            lr[r0 + j] = s_var[r] >= 0 ? ld32(lp, dk) : 0.0f;
+        }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int r = wv * 16 + r0 + j;
-                const int g = s_var[r];
-                const int cn = s_cn[r];
-                float xv = 0.0f, vv = 0.0f;
-                if (g >= 0) {
-                    float acc = 0.0f;
+        for (int j = 0; j < 4; ++j) {
+            const int r = wv * 16 + r0 + j;
+            const int g = s_var[r];
+            const int cn = s_cn[r];
+            float xv = 0.0f, vv = 0.0f;
+            if (g >= 0) {
+                float acc = 0.0f;
 #pragma unroll
-                    for (int q = 0; q < kBatchCopies; ++q)
-                        if (q < cn) acc += zz[j][q] - ll[j][q] * a.inv_rho;
-                    for (int q = kBatchCopies; q < cn; ++q) {
-                        const size_t e = (size_t)a.clist[s_cs[r] + q];
-                        acc += zp[e * Kp + k] - lp[e * Kp + k] * a.inv_rho;
-                    }
-                    const float xh = (acc - s_cost[r]) / (float)cn;
-                    xv = xh < s_lo[r] ? s_lo[r] : (xh > s_hi[r] ? s_hi[r] : xh);
-                    vv = xv + lown[j] * a.inv_rho;
-                    if (s_owner[r]) xq[(size_t)g * Kp + k] = xv;
+                for (int q = 0; q < kBatchCopies; ++q)
+                    if (q < cn) acc += zz[j][q] - ll[j][q] * a.inv_rho;
+                for (int q = kBatchCopies; q < cn; ++q) {
+                    const uint32_t e = (uint32_t)a.clist[s_cs[r] + q] * 256u + lane4;
+                    acc += ld32(zp, e) - ld32(lp, e) * a.inv_rho;
                 }
-                xs[r][lane] = xv;
-                vs[r][lane] = vv;
+                const float xh = (acc - s_cost[r]) / (float)cn;
+                xv = xh < s_lo[r] ? s_lo[r] : (xh > s_hi[r] ? s_hi[r] : xh);
+                vv = xv + lr[r0 + j] * a.inv_rho;
+                if (s_owner[r]) st32(xq, (uint32_t)g * 256u + lane4, xv);
             }
+            xr[r0 + j] = xv;
+            vs[r][lane] = vv;
         }
     }
     __syncthreads();
@@ -227,26 +246,26 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     }
     }
 
-    // the V tile is dead once every wave has its products: its LDS holds the
-    // residual partials
-    __syncthreads();
-    double (*red)[5][32] = reinterpret_cast<double (*)[5][32]>(&vs[0][0]);
-    // ---- phase 3: z = Z + bbar, dual update, residual partials
+    // ---- Z into the V tile's LDS once every wave has read V
     // D[row][col] of a 32 x 32 tile: col = lane % 32, row = 8 (v / 4) + 4 (lane / 32) + v % 4
-    const int col = 32 * nt + l32;
-    const size_t kk = (size_t)(kc + col);
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 16; ++v) vs[32 * m + 8 * (v >> 2) + 4 * grp + (v & 3)][32 * nt + l32] = acc[v];
+    __syncthreads();
+
+    // ---- phase 3: z = Z + bbar, dual update, residual partials (phase 1's layout)
     double s[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int r = 32 * m + 8 * (v >> 2) + 4 * grp + (v & 3);
-        const size_t d = (size_t)w * 64 + r;
+    for (int j = 0; j < 16; ++j) {
+        const int r = wv * 16 + j;
         if (s_var[r] >= 0) {
-            const float zn = acc[v] + a.bbar[d * Kp + kk];
-            const float xv = xs[r][col];
-            const float zo = zp[d * Kp + kk];
-            const float ln = lp[d * Kp + kk] + a.rho * (xv - zn);
-            zq[d * Kp + kk] = zn;
-            lq[d * Kp + kk] = ln;
+            const uint32_t dk = (uint32_t)(w * 64 + r) * 256u + lane4;
+            const float zo = ld32(zp, dk);
+            const float zn = vs[r][lane] + ld32(bbar, dk);
+            const float xv = xr[j];
+            const float ln = lr[j] + a.rho * (xv - zn);
+            st32(zq, dk, zn);
+            st32(lq, dk, ln);
             const double xd = xv, zd = zn;
             s[0] += (xd - zd) * (xd - zd);
             s[1] += (zd - (double)zo) * (zd - (double)zo);
@@ -256,15 +275,13 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
         }
     }
 #pragma unroll
-    for (int i = 0; i < 5; ++i) s[i] += __shfl_xor(s[i], 32, 64);
-    if (grp == 0)
-#pragma unroll
-        for (int i = 0; i < 5; ++i) red[wv][i][l32] = s[i];
+    for (int i = 0; i < 5; ++i) red[wv][i][lane] = s[i];
     __syncthreads();
-    if (m == 0 && grp == 0) {
+    if (wv == 0) {
+        const size_t k = (size_t)(kc + lane);
 #pragma unroll
         for (int i = 0; i < 5; ++i)
-            a.part[((size_t)i * Kp + kk) * a.W + w] = red[wv][i][l32] + red[wv + 1][i][l32];
+            a.part[((size_t)i * Kp + k) * a.W + w] = (red[0][i][lane] + red[1][i][lane]) + (red[2][i][lane] + red[3][i][lane]);
     }
 }
 
@@ -316,10 +333,10 @@ __global__ __launch_bounds__(256) void admm_batch_reduce_kernel(BatchRedArgs r) 
     __syncthreads();
     if (decide) {
         // snapshot x of this scenario at its stop iteration and its objective
-        const float* xs = (t & 1) ? r.x1 : r.x0;
+        const float* xs = ((t & 1) ? r.x1 : r.x0) + (size_t)(k >> 6) * r.n * 64 + (k & 63);
         double obj = 0.0;
         for (int i = threadIdx.x; i < r.n; i += 256) {
-            const double xv = (double)xs[(size_t)i * r.Kp + k];
+            const double xv = (double)xs[(size_t)i * 64];
             r.xout[(size_t)k * r.n + i] = xv;
             obj += r.c[i] * xv;
         }
@@ -348,7 +365,8 @@ __global__ void batch_init_kernel(const double* z0, float* z, float* l, int LP, 
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t tot = (size_t)LP * Kp;
     if (i < tot) {
-        z[i] = (float)z0[i / Kp];
+        // chunk-major: [Kp / 64][LP][64]
+        z[i] = (float)z0[(i >> 6) % (size_t)LP];
         l[i] = 0.0f;
     }
     if (i < (size_t)K) state[i] = 0;

@@ -44,8 +44,9 @@ namespace opf {
 // budget (serving, where one launch holds several solves); otherwise the
 // budget covers every workgroup of the launch.  ADAPT: the penalty follows
 // the residual-balancing ring of the control block (a separate instantiation,
-// so the fixed-penalty kernel keeps its registers).
-template <typename T, int WPB, bool PER_WG_LDS, bool ADAPT>
+// so the fixed-penalty kernel keeps its registers).  RB: workgroup records
+// the reducer's threads load at once.
+template <typename T, int WPB, bool PER_WG_LDS, bool ADAPT, int RB = kBatch>
 __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int* error, long long spin_limit) {
     constexpr int NT = WPB * 64;
     constexpr int W = Tag<T>::W;
@@ -59,7 +60,7 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
     Ctrl* ctrl = a.ctrl;
     const long long t0 = ctrl->iter;
     if (b == G) {
-        reducer_loop<T, NT, ADAPT>(a, G, t0, error, spin_limit);
+        reducer_loop<T, NT, ADAPT, RB>(a, G, t0, error, spin_limit);
         return;
     }
     const int w = b * WPB + wv;
@@ -342,7 +343,9 @@ __global__ __launch_bounds__(kServeWPB * 64) void admm_serve_kernel(const InstDe
     const InstDesc& D = descs[wk.x];
     if (D.ctrl->stop) return;               // finished solves stay resident until retired
     const InstanceView<T> v = view_of<T>(D, s);
-    persistent_instance<T, kServeWPB, true, false>(v, wk.y, D.blocks, s.error, s.spin_limit);
+    // the reducer loads two records per thread at once (three: 136 instead of
+    // 118 VGPRs in FP32, one workgroup fewer per compute unit)
+    persistent_instance<T, kServeWPB, true, false, 2>(v, wk.y, D.blocks, s.error, s.spin_limit);
 }
 
 // Before a serving launch: each work item prepares its own part of its solve

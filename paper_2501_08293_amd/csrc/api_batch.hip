@@ -40,8 +40,8 @@ struct opf_admm_batch {
     float* Fv = nullptr;            // per-scenario factors of the varying wavefronts
     int fv_cols = 0;
     int vary_waves = 0;             // end of the prefix of wavefronts holding the varying components
-    int *var = nullptr, *meta = nullptr, *cstart = nullptr, *ccnt = nullptr, *clist = nullptr;
-    float *lo = nullptr, *hi = nullptr, *cost = nullptr, *bbar = nullptr;
+    int *sdesc = nullptr, *scopy = nullptr, *meta = nullptr, *clist = nullptr;   // see BatchArgs
+    float *sval = nullptr, *bbar = nullptr;
     float* z[2] = {nullptr, nullptr};
     float* l[2] = {nullptr, nullptr};
     float* x[2] = {nullptr, nullptr};
@@ -101,8 +101,8 @@ int bupload(opf_admm_batch* h, P** out, const std::vector<Q>& src) {
 void args_of(opf_admm_batch* h, BatchArgs& a, BatchRedArgs& r) {
     a.Fp = h->Fp; a.terms = h->terms;
     a.wave_var = h->wave_var; a.Fv = h->Fv; a.fv_cols = h->fv_cols; a.vary_waves = h->vary_waves;
-    a.var = h->var; a.meta = h->meta; a.cstart = h->cstart; a.ccnt = h->ccnt; a.clist = h->clist;
-    a.lo = h->lo; a.hi = h->hi; a.cost = h->cost; a.bbar = h->bbar;
+    a.sdesc = reinterpret_cast<const int4*>(h->sdesc); a.sval = reinterpret_cast<const float4*>(h->sval);
+    a.scopy = reinterpret_cast<const int4*>(h->scopy); a.meta = h->meta; a.clist = h->clist; a.bbar = h->bbar;
     a.z0 = h->z[0]; a.z1 = h->z[1]; a.l0 = h->l[0]; a.l1 = h->l[1]; a.x0 = h->x[0]; a.x1 = h->x[1];
     a.part = h->part; a.ctrl = h->ctrl;
     a.W = h->lay.waves; a.Kp = h->Kp; a.K = h->K; a.n = h->lay.n;
@@ -122,7 +122,7 @@ void args_of(opf_admm_batch* h, BatchArgs& a, BatchRedArgs& r) {
 // fastest kept; decisions are cached per problem shape (tune_cache.h).  All
 // orders compute the same values.
 int tune_batch(opf_admm_batch* h) {
-    const std::string key = "batch/" + std::to_string(h->lay.waves) + "/" + std::to_string(h->Kp) + "/" +
+    const std::string key = "batch/r" + std::to_string(kBatchKernelRev) + "/" + std::to_string(h->lay.waves) + "/" + std::to_string(h->Kp) + "/" +
                             std::to_string(h->terms) + "/" + std::to_string(h->vary_waves) + "/" +
                             std::to_string(h->lay.L) + "/" + std::to_string(h->lay.sum_ns2);
     std::vector<int> got;
@@ -299,6 +299,9 @@ int opf_admm_setup_batch_ex(const opf_problem* p, const double* b_scen, int32_t 
         opf_admm_destroy_batch(h);
         return berr(nullptr, code, m);
     };
+    // the step kernel addresses one 64-scenario chunk of the state with 32-bit byte offsets
+    if ((size_t)h->LP * 256 > 0xffffffffull || (size_t)h->lay.n * 256 > 0xffffffffull)
+        return fail(berr(h, OPF_EINVAL, "batched scenarios: more than 16M slots or variables"));
     if (h->user_stream) h->stream = h->user_stream;
     else if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
         return fail(berr(h, OPF_EHIP, "hipStreamCreate failed"));
@@ -312,15 +315,41 @@ int opf_admm_setup_batch_ex(const opf_problem* p, const double* b_scen, int32_t 
         if ((rc = bupload(h, &h->wave_var, wave_var))) return fail(rc);
         if ((rc = bupload(h, &h->Fv, Fv))) return fail(rc);
     }
-    if ((rc = bupload(h, &h->var, L.var))) return fail(rc);
+    {
+        // per-slot records of the step kernel (one 16-byte load each, no
+        // dependent loads): variable, copies, copy-list offset, owner; cost and
+        // bounds; the first kBatchCopies copies, then the slot itself
+        const size_t LPs = (size_t)h->LP;
+        std::vector<int> sd(LPs * 4, 0), sc(LPs * 8);
+        std::vector<float> sv(LPs * 4, 0.0f);
+        for (size_t d = 0; d < LPs; ++d) {
+            const int g = L.var[d];
+            const int cn = g >= 0 ? L.copy_cnt[d] : 0, cs = g >= 0 ? L.copy_start[d] : 0;
+            sd[4 * d + 0] = g;
+            sd[4 * d + 1] = cn;
+            sd[4 * d + 2] = cs;
+            sd[4 * d + 3] = g >= 0 ? (L.meta[d] >> 16) & 1 : 0;
+            if (g >= 0) {
+                sv[4 * d + 0] = (float)L.cost[d];
+                sv[4 * d + 1] = (float)L.lo[d];
+                sv[4 * d + 2] = (float)L.hi[d];
+            }
+            for (int q = 0; q < 8; ++q) sc[8 * d + q] = q < std::min(cn, kBatchCopies) ? L.copy_list[cs + q] : (int)d;
+        }
+        if ((rc = bupload(h, &h->sdesc, sd))) return fail(rc);
+        if ((rc = bupload(h, &h->sval, sv))) return fail(rc);
+        if ((rc = bupload(h, &h->scopy, sc))) return fail(rc);
+    }
     if ((rc = bupload(h, &h->meta, L.meta))) return fail(rc);
-    if ((rc = bupload(h, &h->cstart, L.copy_start))) return fail(rc);
-    if ((rc = bupload(h, &h->ccnt, L.copy_cnt))) return fail(rc);
     if ((rc = bupload(h, &h->clist, L.copy_list))) return fail(rc);
-    if ((rc = bupload(h, &h->lo, L.lo))) return fail(rc);
-    if ((rc = bupload(h, &h->hi, L.hi))) return fail(rc);
-    if ((rc = bupload(h, &h->cost, L.cost))) return fail(rc);
-    if ((rc = bupload(h, &h->bbar, bb))) return fail(rc);
+    {
+        // b-bar per slot and scenario, [LP][Kp] -> chunk-major [Kp / 64][LP][64]
+        const size_t LPs = (size_t)h->LP, Kp = (size_t)h->Kp;
+        std::vector<float> cm(bb.size());
+        for (size_t d = 0; d < LPs; ++d)
+            for (size_t k = 0; k < Kp; ++k) cm[((k >> 6) * LPs + d) * 64 + (k & 63)] = bb[d * Kp + k];
+        if ((rc = bupload(h, &h->bbar, cm))) return fail(rc);
+    }
     if ((rc = bupload(h, &h->z0, L.z0))) return fail(rc);
     if ((rc = bupload(h, &h->c, L.c_full))) return fail(rc);
     const size_t st = (size_t)h->LP * h->Kp;

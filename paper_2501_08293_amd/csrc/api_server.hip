@@ -40,10 +40,12 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 constexpr int kWPB = 4;              // wavefronts per workgroup of the shared launch
-// factor columns per workgroup held in LDS: 48 KiB in either precision, so
-// that the launch stays register-bound at three workgroups per compute unit
+// factor columns per workgroup held in LDS.  FP64 (147 VGPRs, three
+// workgroups per compute unit): 48 KiB.  FP32 (118 VGPRs, four workgroups per
+// compute unit): 38 KiB, which with the kernel's own 1.6 KiB keeps four
+// workgroups within the 160 KiB of one compute unit
 constexpr int kServeLdsCols64 = 96;
-constexpr int kServeLdsCols32 = 192;
+constexpr int kServeLdsCols32 = 152;
 constexpr size_t kAlign = 256;
 
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }

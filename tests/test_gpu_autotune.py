@@ -54,9 +54,13 @@ def test_each_batch_order_gives_the_same_bits(tmp_path, monkeypatch, order):
     B = scenario_rhs(inst, scenario_load_factors(f, 70, seed=5))
     s = _batch(inst, B, rho=100.0, eps_rel=1e-12, max_iter=40, check_every=8)
     ref = s.solve()
-    info = s.info()
     s.close()
-    key = f"batch/{info.waves}/128/3/0/{info.L}/{info.sum_ns2}"
+    # the problem's cache key, as the tuner writes it, then a fresh cache file
+    # (decisions are kept in memory per file) holding the order
+    probe = tmp_path / "probe.txt"
+    monkeypatch.setenv("OPF_ADMM_TUNE_CACHE", str(probe))
+    _batch(inst, B, rho=100.0, eps_rel=1e-12, max_iter=40, check_every=8, autotune=True).close()
+    key = [l for l in probe.read_text().splitlines() if l.startswith("batch/")][-1].split("\t")[0]
     cache = tmp_path / "tune.txt"
     cache.write_text(f"{key}\t{order}\n")
     monkeypatch.setenv("OPF_ADMM_TUNE_CACHE", str(cache))
