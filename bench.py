@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--workgroup-order", type=int, default=0, choices=[0, 1],
                     help="persistent kernel: 0 = hardware workgroup order, 1 = XCD-contiguous packing ranges")
     ap.add_argument("--check-every", type=int, default=1024)
+    ap.add_argument("--max-iter", type=int, default=1_000_000, help="iteration cap of the single-instance solve")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="time this many iterations per step instead of solving to tolerance")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -210,6 +211,7 @@ def single_instance(args, torch):
     kern = {"auto": 0, "step": 1, "persistent": 2, "tiled": 3}[args.kernel]
     flat = (inst.n, inst.c, inst.lb, inst.ub, inst.var_kind) + tuple(inst.flat())
     solver = Solver(*flat, rho=100.0, eps_rel=args.eps, precision=prec, check_every=args.check_every,
+                    max_iter=args.max_iter,
                     kernel=kern, block_waves=args.block_waves, workgroup_order=args.workgroup_order,
                     autotune=args.autotune, stream=stream.cuda_stream)
     info = solver.info()
@@ -248,7 +250,7 @@ def single_instance(args, torch):
         dom_name = dom_name.replace("persistent", "step")
         dom_launches = dom_iters
     elif info.kernel == 3:
-        dom_name = dom_name.replace("persistent", "tiled")
+        dom_name = dom_name.replace("persistent", "tiled_pair" if info.tiled_pair else "tiled")
     achieved = dom_bytes * dom_iters / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     tr = traffic_from_profiles(args.workload, args.precision)
     traffic = None

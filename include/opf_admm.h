@@ -114,7 +114,8 @@ typedef struct opf_problem {
 typedef struct opf_admm_options {
     double  rho;            /* ADMM penalty (> 0) */
     double  eps_rel;        /* relative tolerance of the termination test (> 0) */
-    int64_t max_iter;       /* iteration cap (>= 1) */
+    int64_t max_iter;       /* iteration cap (>= 1); MIXED with polish: a cap for each of the two phases (the
+                               FP32 bulk phase, then up to max_iter FP64 polish iterations) */
     int32_t precision;      /* OPF_PREC_FP64 or OPF_PREC_MIXED */
     int32_t polish;         /* MIXED only: 1 = finish with FP64 iterations until the FP64 test holds */
     int32_t check_every;    /* STEP schedule: iterations enqueued between host checks of the stop flag */
