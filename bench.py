@@ -297,6 +297,9 @@ def single_instance(args, torch):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            # achieved counts the algorithmic bytes (factors once per iteration although they stay in LDS);
+            # the HBM rate the counters measure for the same launch:
+            "traffic_gbs": round(traffic / (dom_ms / max(dom_launches, 1) * 1e-3) / 1e9, 1) if traffic else None,
             "kernel": dom_name,
             "bytes_per_iteration": dom_bytes,
             "avg_launch_ms": round(dom_ms / max(dom_launches, 1), 4),
