@@ -413,8 +413,22 @@ typedef struct opf_server_options {
                                   polls the stop flags and admits / retires solves */
     int32_t setup_threads;     /* host threads for row reduction / factors / packing */
     int32_t warm_start;        /* 1: use resident states of the same family */
-    int32_t reserved[5];
+    int32_t admission;         /* order in which waiting requests are offered the free co-resident
+                                  capacity: OPF_ADMIT_LARGEST_FIRST (default) or OPF_ADMIT_ARRIVAL; in
+                                  either order a request that does not fit is passed over for later ones */
+    int32_t max_wait_ms;       /* starvation guard (0: off; default 500): once a request that does not fit
+                                  has waited this long since submission, and the solves holding the
+                                  capacity it needs are all smaller than it, smaller requests are no longer
+                                  admitted ahead of it (the capacity drains to it as those solves end) */
+    int32_t reserved[3];
 } opf_server_options;
+
+/* Largest first: the solves of the most workgroups start as soon as they fit
+   and smaller ones fill the remaining capacity (on mixed-size traffic the
+   largest solves are the critical path: with arrival order, smaller requests
+   admitted behind a large one keep taking the capacity it waits for). */
+#define OPF_ADMIT_LARGEST_FIRST 0
+#define OPF_ADMIT_ARRIVAL       1
 
 typedef struct opf_served {
     int64_t request_id;

@@ -40,6 +40,9 @@ OPF_RHO_RELATIVE = 0
 OPF_RHO_PLAIN = 1
 OPF_RHO_LAG = 4
 
+OPF_ADMIT_LARGEST_FIRST = 0
+OPF_ADMIT_ARRIVAL = 1
+
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBOUNDS", -3: "EUNCOVERED",
                 -4: "EINFEASIBLE_COMPONENT", -5: "ENOMEM", -6: "EHIP", -7: "ENUMERIC", -8: "EHANG"}
 
@@ -109,7 +112,8 @@ class opf_batch_result(C.Structure):
 class opf_server_options(C.Structure):
     _fields_ = [("admm", opf_admm_options), ("arena_bytes", C.c_int64), ("warm_bytes", C.c_int64),
                 ("max_slots", C.c_int32), ("max_workgroups", C.c_int32), ("iters_per_poll", C.c_int32),
-                ("setup_threads", C.c_int32), ("warm_start", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("setup_threads", C.c_int32), ("warm_start", C.c_int32), ("admission", C.c_int32),
+                ("max_wait_ms", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class opf_served(C.Structure):
@@ -554,7 +558,8 @@ class Server:
 
     def __init__(self, *, rho=100.0, eps_rel=1e-4, max_iter=1_000_000, arena_bytes=4 << 30, warm_bytes=1 << 30,
                  max_slots=256, max_workgroups=8192, iters_per_poll=256, setup_threads=4, warm_start=True,
-                 precision=OPF_PREC_FP64, polish=True, spin_limit=0, stream=0):
+                 precision=OPF_PREC_FP64, polish=True, spin_limit=0, admission=None, max_wait_ms=None,
+                 stream=0):
         lib = load()
         o = opf_server_default_options()
         o.admm.rho = rho
@@ -570,6 +575,10 @@ class Server:
         o.iters_per_poll = iters_per_poll
         o.setup_threads = setup_threads
         o.warm_start = int(bool(warm_start))
+        if admission is not None:
+            o.admission = int(admission)
+        if max_wait_ms is not None:
+            o.max_wait_ms = int(max_wait_ms)
         h = C.c_void_p()
         rc = lib.opf_server_create(C.byref(o), C.c_void_p(stream or None), C.byref(h))
         if rc != OPF_OK:

@@ -484,7 +484,41 @@ bool admit_ready(opf_server* s) {
         std::lock_guard<std::mutex> lk(s->mu);
         cand.swap(s->ready);
     }
-    for (auto& r : cand) {
+    // offer order (requests left waiting keep their arrival order)
+    std::vector<size_t> order(cand.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    if (s->opt.admission == OPF_ADMIT_LARGEST_FIRST)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t a, size_t b) { return cand[a]->lay.blocks > cand[b]->lay.blocks; });
+    std::vector<char> waiting(cand.size(), 0);
+    // starvation guard: the largest request that has waited max_wait_ms and
+    // does not fit, when only smaller solves hold the capacity it needs
+    const int limit_run = std::min(s->opt.max_workgroups, s->mixed ? s->cap32 : s->cap64);
+    const int used_run = s->mixed ? s->blocks32 : s->blocks64;
+    const Request* hold_for = nullptr;
+    if (s->opt.max_wait_ms > 0) {
+        const auto now = clk::now();
+        for (auto& r : cand) {
+            const int need = r->lay.blocks + 1;
+            if (used_run + need <= limit_run || need > limit_run || ms_since(r->t_submit, now) < s->opt.max_wait_ms)
+                continue;
+            if (!hold_for || need > hold_for->lay.blocks + 1) hold_for = r.get();
+        }
+        if (hold_for) {
+            const int need = hold_for->lay.blocks + 1;
+            int smaller = 0;                      // capacity held by smaller solves of the same launch
+            for (const Slot& sl : s->slots)
+                if (sl.used && !sl.waiting && (sl.fp32 != 0) == s->mixed && sl.desc.blocks + 1 < need)
+                    smaller += sl.desc.blocks + 1;
+            if (limit_run - used_run + smaller < need) hold_for = nullptr;   // larger solves block it: no hold
+        }
+    }
+    for (size_t oi : order) {
+        auto& r = cand[oi];
+        if (hold_for && r.get() != hold_for) {
+            waiting[oi] = 1;
+            continue;
+        }
         int free_slot = -1;
         for (int q = 0; q < (int)s->slots.size(); ++q)
             if (!s->slots[q].used) { free_slot = q; break; }
@@ -505,8 +539,10 @@ bool admit_ready(opf_server* s) {
             push_result(s, *r, OPF_EHIP, nullptr, 0);   // device failure: report and drop
             continue;
         }
-        if (rc == 0) keep.push_back(std::move(r));        // no room now; later ones may fit
+        if (rc == 0) waiting[oi] = 1;                      // no room now; later ones may fit
     }
+    for (size_t i = 0; i < cand.size(); ++i)
+        if (waiting[i]) keep.push_back(std::move(cand[i]));
     if (!keep.empty()) {
         std::lock_guard<std::mutex> lk(s->mu);
         while (!keep.empty()) {
@@ -699,6 +735,8 @@ void opf_server_default_options(opf_server_options* o) {
     o->iters_per_poll = 256;
     o->setup_threads = 4;
     o->warm_start = 1;
+    o->admission = OPF_ADMIT_LARGEST_FIRST;
+    o->max_wait_ms = 500;
 }
 
 int opf_server_create(const opf_server_options* o, void* hip_stream, opf_server** out) {
@@ -709,6 +747,7 @@ int opf_server_create(const opf_server_options* o, void* hip_stream, opf_server*
     else opf_server_default_options(&opt);
     if (!(opt.admm.rho > 0) || !(opt.admm.eps_rel > 0) || opt.admm.max_iter < 1 || opt.arena_bytes < (1 << 20) ||
         opt.max_slots < 1 || opt.max_workgroups < 1 || opt.iters_per_poll < 1 ||
+        (opt.admission != OPF_ADMIT_LARGEST_FIRST && opt.admission != OPF_ADMIT_ARRIVAL) || opt.max_wait_ms < 0 ||
         (opt.admm.precision != OPF_PREC_FP64 && opt.admm.precision != OPF_PREC_MIXED))
         return serr(nullptr, OPF_EINVAL, "invalid server options");
     if (opt.admm.rho_every != 0 || opt.admm.local_updates > 1)

@@ -82,6 +82,20 @@ def test_server_rejects_balancing():
     assert not h.value
 
 
+def test_server_admission_options():
+    """Largest-first admission with a 500 ms starvation guard by default; other
+    orders and negative waits are rejected before any device work."""
+    binding, lib = _lib()
+    o = binding.opf_server_default_options()
+    assert o.admission == binding.OPF_ADMIT_LARGEST_FIRST and o.max_wait_ms == 500
+    h = C.c_void_p()
+    for field, bad in (("admission", 2), ("admission", -1), ("max_wait_ms", -5)):
+        o = binding.opf_server_default_options()
+        setattr(o, field, bad)
+        assert lib.opf_server_create(C.byref(o), None, C.byref(h)) == binding.OPF_EINVAL, field
+        assert not h.value
+
+
 def test_rejects_lb_above_ub(inst):
     cm, cn, A, b, idx = inst.flat()
     lb = inst.lb.copy()
@@ -175,3 +189,16 @@ def test_binding_layouts_match_the_c_compiler(tmp_path):
         assert got[(st, "size")] == C.sizeof(cls), st
         for field, _t in cls._fields_:
             assert got[(st, field)] == getattr(cls, field).offset, (st, field)
+
+
+def test_binding_constants_match_the_header():
+    """Every OPF_* integer constant the binding defines equals the header's #define."""
+    import re
+    binding, _ = _lib()
+    text = open(os.path.join(ROOT, "include", "opf_admm.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(OPF_[A-Z0-9_]+)\s+\(?(-?\d+)\)?\s", text)}
+    names = [n for n in dir(binding) if n.startswith("OPF_") and isinstance(getattr(binding, n), int)]
+    assert len(names) >= 15
+    for n in names:
+        assert n in defs, n
+        assert getattr(binding, n) == defs[n], n

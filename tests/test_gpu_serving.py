@@ -275,3 +275,37 @@ def test_warm_started_solve_alone_and_in_mix_give_identical_bits(mix):
     assert alone["warm_components"] > 0 and alone["warm_components"] == inmix["warm_components"]
     assert alone["iterations"] == inmix["iterations"] and alone["iterations_fp32"] == inmix["iterations_fp32"]
     assert np.array_equal(alone["x"], inmix["x"])
+
+
+def test_starvation_guard_admits_a_large_solve_ahead_of_later_small_ones():
+    """Under a workgroup cap that holds the large solve only beside one small
+    one, a stream of small requests would keep the capacity it needs taken;
+    with the starvation guard (1 ms) the small requests that arrive after it
+    are held back until it is admitted, and every request converges."""
+    from paper_2501_08293_amd import Server
+    small = [build_instance(by_name("13bus", s)) for s in range(3)]
+    big = build_instance(by_name("123bus", 0))
+    _say("[gpu] serving: starvation guard, 123bus among 45 13bus requests, max_workgroups 16")
+    srv = Server(rho=RHO, eps_rel=1e-4, warm_start=False, iters_per_poll=64, arena_bytes=256 << 20,
+                 max_workgroups=16, max_wait_ms=1)
+    t_sub = {}
+    ids = []
+    for k in range(5):
+        i = srv.submit(*_args(small[k % 3]), family=100 + k)
+        t_sub[i] = time.perf_counter()
+        ids.append(i)
+    time.sleep(0.005)
+    bid = srv.submit(*_args(big), family=1)
+    t_sub[bid] = time.perf_counter()
+    later = []
+    for k in range(40):
+        i = srv.submit(*_args(small[k % 3]), family=200 + k)
+        t_sub[i] = time.perf_counter()
+        later.append(i)
+    res = _drain(srv, ids + [bid] + later)
+    srv.close()
+    assert all(r["status"] == 0 for r in res.values())
+    admit = {i: t_sub[i] + res[i]["queue_ms"] * 1e-3 for i in res}
+    after = sum(1 for i in later if admit[i] >= admit[bid] - 1e-3)
+    _say(f"  large solve queued {res[bid]['queue_ms']:.1f} ms; {after} of 40 later small requests admitted after it")
+    assert after >= 30
