@@ -33,13 +33,13 @@ def _same(a, b):
         assert a[k] == b[k], k
 
 
-@pytest.mark.parametrize("kernel,precision", [(2, 0), (2, 1), (1, 0)],
-                         ids=["persistent-fp64", "persistent-mixed", "step-fp64"])
-def test_noalloc_equals_solve_on_two_calls_second_smaller(kernel, precision):
+@pytest.mark.parametrize("kernel,precision,bw", [(2, 0, 0), (2, 1, 0), (1, 0, 0), (3, 1, 1), (3, 0, 1)],
+                         ids=["persistent-fp64", "persistent-mixed", "step-fp64", "tiled-mixed", "tiled-fp64"])
+def test_noalloc_equals_solve_on_two_calls_second_smaller(kernel, precision, bw):
     for name in ("123bus", "13bus"):
-        _say(f"[gpu] allocation-free solve {name} kernel={kernel} precision={precision}")
+        _say(f"[gpu] allocation-free solve {name} kernel={kernel} precision={precision} block_waves={bw}")
         inst = build_instance(by_name(name, 0))
-        s = _solver(inst, eps_rel=1e-4, kernel=kernel, precision=precision, check_every=128)
+        s = _solver(inst, eps_rel=1e-4, kernel=kernel, precision=precision, check_every=128, block_waves=bw)
         ref = s.solve()
         got = s.solve(noalloc=True)
         s.close()
