@@ -434,6 +434,7 @@ def batch_leg(args, torch):
         "precision": "bf16 three-term split products on MFMA, fp32 accumulate, fp32 state, fp64 residual sums",
         "workgroup_order": {0: "hardware, wavefront-major", 1: "XCD-contiguous, wavefront-major",
                             2: "hardware, chunk-major", 3: "XCD-contiguous, chunk-major"}.get(info.batch_order),
+        "scenario_groups": info.batch_groups,
         "setup_s_with_autotune": round(setup_s, 2),
         "zip_loads": zip_batch_timing(args, torch, K) if not fixed else None,
     }

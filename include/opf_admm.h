@@ -233,7 +233,9 @@ typedef struct opf_admm_info {
     int32_t tiled_pair;        /* TILED: 1 when the two-tile kernel runs (each workgroup keeps two tiles in
                                   flight), 0 for the kernel that takes its tiles in turn (precision of the
                                   bulk phase) */
-    int32_t reserved[2];
+    int32_t batch_groups;      /* batched path: scenario groups iterated by concurrent launches on their own
+                                  streams (the 64-scenario chunks split into contiguous ranges) */
+    int32_t reserved[1];
 } opf_admm_info;
 
 typedef struct opf_admm_handle opf_admm_handle;

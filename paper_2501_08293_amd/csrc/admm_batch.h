@@ -7,7 +7,7 @@
 
 namespace opf {
 
-constexpr int kBatchKernelRev = 2;   // revision of the step kernel (tuning decisions are kept per revision)
+constexpr int kBatchKernelRev = 3;   // revision of the step kernel (tuning decisions are kept per revision)
 constexpr int kBatchCopies = 6;    // copies per variable gathered from the slot record (more: from the copy list)
 
 // ---- batched same-topology scenarios (see admm_batch.hip)
@@ -42,6 +42,7 @@ struct BatchArgs {
     int W, Kp, K, n;
     float rho, inv_rho;
     int order;              // workgroup order: bit 0 XCD-contiguous packing ranges, bit 1 chunk-major
+    int c0, nc;             // this launch's 64-scenario chunks: [c0, c0 + nc)
 };
 
 struct BatchRedArgs {
@@ -56,11 +57,16 @@ struct BatchRedArgs {
     const double* c;
     int W, Kp, K, n;
     double rho, eps_rel;
+    int k0;                 // this launch's scenarios: [k0, k0 + gridDim.x)
 };
 
 
-hipError_t launch_batch_iteration(const BatchArgs& a, const BatchRedArgs& r, hipStream_t st);
-hipError_t launch_batch_init(const double* z0, float* z, float* l, int LP, int Kp, BatchCtrl* ctrl, int* state,
-                             int K, long long max_iter, hipStream_t st);
+// One iteration of the scenario group whose chunks a.c0 .. a.c0 + a.nc - 1
+// and scenarios r.k0 .. r.k0 + kn - 1 are given (kn: its scenarios below K).
+hipError_t launch_batch_iteration(const BatchArgs& a, const BatchRedArgs& r, int kn, hipStream_t st);
+// State of every scenario at the default start, and the control blocks of
+// the `groups` scenario groups.
+hipError_t launch_batch_init(const double* z0, float* z, float* l, int LP, int Kp, BatchCtrl* ctrl, int groups,
+                             int* state, int K, long long max_iter, hipStream_t st);
 
 }  // namespace opf

@@ -24,6 +24,7 @@
 // iteration; the batch runs until every scenario has stopped.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "../../include/opf_admm.h"
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
     __shared__ double red[4][5][64];              // residual partials per wave and scenario
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int KB = a.Kp >> 6;
+    const int KB = a.nc;                       // chunks of this launch
     const int nvb = a.vary_waves * KB, bx = (int)blockIdx.x;
     const int rest = (int)gridDim.x - nvb;
     int pos = bx < nvb ? bx : nvb + logical_block(bx - nvb, rest, a.order & 1);
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
         pos = nvb + (q % wr) * KB + q / wr;
     }
     const int w = pos / KB;
-    const int chunk = pos - w * KB, kc = chunk * 64;
+    const int chunk = a.c0 + (pos - w * KB), kc = chunk * 64;
     // state of this 64-scenario chunk: [slot][64] (x: [variable][64])
     const size_t sb = (size_t)chunk * a.W * 64 * 64, xb = (size_t)chunk * a.n * 64;
     const float* zp = (odd ? a.z0 : a.z1) + sb;
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(256) void admm_batch_reduce_kernel(BatchRedArgs r) 
     BatchCtrl* ctrl = r.ctrl;
     if (ctrl->stop) return;
     const long long t = ctrl->iter + 1;
-    const int k = blockIdx.x;
+    const int k = r.k0 + (int)blockIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __shared__ double red[4][5];
     __shared__ int decide;
@@ -354,14 +355,14 @@ __global__ __launch_bounds__(256) void admm_batch_reduce_kernel(BatchRedArgs r) 
         if (old == gridDim.x - 1) {
             const int done = __hip_atomic_load(&ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ctrl->iter = t;
-            if (done >= r.K || t >= ctrl->max_iter) ctrl->stop = 1;
+            if (done >= (int)gridDim.x || t >= ctrl->max_iter) ctrl->stop = 1;
             ctrl->arrive = 0u;
         }
     }
 }
 
 __global__ void batch_init_kernel(const double* z0, float* z, float* l, int LP, int Kp, BatchCtrl* ctrl,
-                                  int* state, int K, long long max_iter) {
+                                  int groups, int* state, int K, long long max_iter) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t tot = (size_t)LP * Kp;
     if (i < tot) {
@@ -370,26 +371,28 @@ __global__ void batch_init_kernel(const double* z0, float* z, float* l, int LP, 
         l[i] = 0.0f;
     }
     if (i < (size_t)K) state[i] = 0;
-    if (i == 0) {
-        ctrl->iter = 0;
-        ctrl->max_iter = max_iter;
-        ctrl->stop = 0;
-        ctrl->done = 0;
-        ctrl->arrive = 0u;
+    if (i < (size_t)groups) {
+        ctrl[i].iter = 0;
+        ctrl[i].max_iter = max_iter;
+        ctrl[i].stop = 0;
+        ctrl[i].done = 0;
+        ctrl[i].arrive = 0u;
     }
 }
 
-hipError_t launch_batch_iteration(const BatchArgs& a, const BatchRedArgs& r, hipStream_t st) {
-    hipLaunchKernelGGL(admm_batch_step_kernel, dim3(a.W * (a.Kp / 64)), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(admm_batch_reduce_kernel, dim3(r.K), dim3(256), 0, st, r);
+hipError_t launch_batch_iteration(const BatchArgs& a, const BatchRedArgs& r, int kn, hipStream_t st) {
+    if (a.nc < 1 || kn < 1 || a.c0 < 0 || a.c0 + a.nc > a.Kp / 64 || r.k0 < 0 || r.k0 + kn > r.K)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(admm_batch_step_kernel, dim3(a.W * a.nc), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(admm_batch_reduce_kernel, dim3(kn), dim3(256), 0, st, r);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_init(const double* z0, float* z, float* l, int LP, int Kp, BatchCtrl* ctrl, int* state,
-                             int K, long long max_iter, hipStream_t st) {
-    const size_t tot = (size_t)LP * Kp;
+hipError_t launch_batch_init(const double* z0, float* z, float* l, int LP, int Kp, BatchCtrl* ctrl, int groups,
+                             int* state, int K, long long max_iter, hipStream_t st) {
+    const size_t tot = std::max((size_t)LP * Kp, (size_t)std::max(K, groups));
     hipLaunchKernelGGL(batch_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, z0, z, l, LP, Kp,
-                       ctrl, state, K, max_iter);
+                       ctrl, groups, state, K, max_iter);
     return hipGetLastError();
 }
 

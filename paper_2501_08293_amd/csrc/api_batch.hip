@@ -25,6 +25,8 @@ std::mutex g_berr_mu;
 std::string g_batch_setup_err;
 }  // namespace
 
+constexpr int kMaxGroups = 4;
+
 struct opf_admm_batch {
     opf_admm_options opt;
     hipStream_t user_stream = nullptr;
@@ -48,15 +50,24 @@ struct opf_admm_batch {
     double* part = nullptr;
     double* z0 = nullptr;
     double* c = nullptr;
-    BatchCtrl* ctrl = nullptr;
-    BatchCtrl* ctrl_host = nullptr;
+    BatchCtrl* ctrl = nullptr;          // [kMaxGroups] one control block per scenario group
+    BatchCtrl* ctrl_host = nullptr;     // [kMaxGroups] pinned copies
     int* state = nullptr;
     long long* iters = nullptr;
     double* res = nullptr;
     double* objective = nullptr;
     double* xout = nullptr;
-    hipGraphExec_t graph = nullptr;
-    int graph_k = 0;
+    // Scenario groups: the 64-scenario chunks split into `groups` contiguous
+    // ranges, each iterated by its own launches on its own stream (streams[0]
+    // is the handle's stream), so that one group's launch fills the compute
+    // units the other's ending launch leaves idle.  Scenarios are independent:
+    // every grouping computes the same values.
+    int groups = 1;
+    hipStream_t streams[kMaxGroups] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kMaxGroups] = {};
+    hipGraphExec_t graph[kMaxGroups] = {};
+    int graph_k = 0, graph_groups = 0, graph_order = -1;
     int order = 1;                  // workgroup order of the step kernel (BatchArgs::order)
 };
 
@@ -98,6 +109,16 @@ int bupload(opf_admm_batch* h, P** out, const std::vector<Q>& src) {
     return 0;
 }
 
+// Chunks [c0, c0 + nc) and scenarios [k0, k0 + kn) of group g of G.
+void group_range(const opf_admm_batch* h, int g, int G, int* c0, int* nc, int* k0, int* kn) {
+    const int KB = h->Kp / 64;
+    const int a = g * KB / G, b = (g + 1) * KB / G;
+    *c0 = a;
+    *nc = b - a;
+    *k0 = a * 64;
+    *kn = std::min(h->K, b * 64) - a * 64;
+}
+
 void args_of(opf_admm_batch* h, BatchArgs& a, BatchRedArgs& r) {
     a.Fp = h->Fp; a.terms = h->terms;
     a.wave_var = h->wave_var; a.Fv = h->Fv; a.fv_cols = h->fv_cols; a.vary_waves = h->vary_waves;
@@ -108,26 +129,55 @@ void args_of(opf_admm_batch* h, BatchArgs& a, BatchRedArgs& r) {
     a.W = h->lay.waves; a.Kp = h->Kp; a.K = h->K; a.n = h->lay.n;
     a.rho = (float)h->opt.rho; a.inv_rho = (float)(1.0 / h->opt.rho);
     a.order = h->order;
+    a.c0 = 0; a.nc = h->Kp / 64;
+    r.k0 = 0;
     r.part = h->part; r.ctrl = h->ctrl; r.state = h->state; r.iters = h->iters; r.res = h->res;
     r.objective = h->objective; r.xout = h->xout; r.x0 = h->x[0]; r.x1 = h->x[1]; r.c = h->c;
     r.W = h->lay.waves; r.Kp = h->Kp; r.K = h->K; r.n = h->lay.n;
     r.rho = h->opt.rho; r.eps_rel = h->opt.eps_rel;
 }
 
+// Arguments of group g of G; *kn receives its scenario count.
+void group_args(opf_admm_batch* h, int g, int G, BatchArgs& a, BatchRedArgs& r, int* kn) {
+    args_of(h, a, r);
+    int c0, nc, k0;
+    group_range(h, g, G, &c0, &nc, &k0, kn);
+    a.c0 = c0; a.nc = nc; a.ctrl = h->ctrl + g;
+    r.k0 = k0; r.ctrl = h->ctrl + g;
+}
+
+// The extra streams of groups 1.. wait for the handle's stream (fork), and
+// the handle's stream for all of them (join).
+int fork_groups(opf_admm_batch* h, int G) {
+    BHIP(hipEventRecord(h->fork, h->stream));
+    for (int g = 1; g < G; ++g) BHIP(hipStreamWaitEvent(h->streams[g], h->fork, 0));
+    return 0;
+}
+int join_groups(opf_admm_batch* h, int G) {
+    for (int g = 1; g < G; ++g) {
+        BHIP(hipEventRecord(h->join[g], h->streams[g]));
+        BHIP(hipStreamWaitEvent(h->stream, h->join[g], 0));
+    }
+    return 0;
+}
+
 }  // namespace
 
 // Autotuner of the batched iteration: each workgroup order of the step
-// kernel (XCD-contiguous or hardware order, wavefront- or chunk-major) is
-// timed over 64 iterations after 8 untimed ones, on this problem, and the
-// fastest kept; decisions are cached per problem shape (tune_cache.h).  All
-// orders compute the same values.
+// kernel (XCD-contiguous or hardware order, wavefront- or chunk-major) with
+// each number of scenario groups on concurrent streams (1, 2, 4, at most one
+// per 64-scenario chunk) is timed over 64 iterations after 8 untimed ones, on
+// this problem, and the fastest kept; decisions are cached per problem shape
+// (tune_cache.h).  All choices compute the same values.
 int tune_batch(opf_admm_batch* h) {
     const std::string key = "batch/r" + std::to_string(kBatchKernelRev) + "/" + std::to_string(h->lay.waves) + "/" + std::to_string(h->Kp) + "/" +
                             std::to_string(h->terms) + "/" + std::to_string(h->vary_waves) + "/" +
                             std::to_string(h->lay.L) + "/" + std::to_string(h->lay.sum_ns2);
     std::vector<int> got;
-    if (tune_cache_get(key, got) && got.size() == 1) {
+    const int KB = h->Kp / 64;
+    if (tune_cache_get(key, got) && got.size() == 2 && got[1] >= 1 && got[1] <= std::min(KB, kMaxGroups)) {
         h->order = got[0];
+        h->groups = got[1];
         return 0;
     }
     struct Events {
@@ -140,27 +190,40 @@ int tune_batch(opf_admm_batch* h) {
     BHIP(hipEventCreate(&ev.e0));
     BHIP(hipEventCreate(&ev.e1));
     float best = 1e30f;
-    int bo = 1;
-    for (int order : {1, 0, 3, 2}) {
-        h->order = order;
-        BatchArgs a;
-        BatchRedArgs rr;
-        args_of(h, a, rr);
-        BHIP(launch_batch_init(h->z0, h->z[0], h->l[0], h->LP, h->Kp, h->ctrl, h->state, h->K, 1LL << 40, h->stream));
-        for (int i = 0; i < 8; ++i) BHIP(launch_batch_iteration(a, rr, h->stream));
-        BHIP(hipEventRecord(ev.e0, h->stream));
-        for (int i = 0; i < 64; ++i) BHIP(launch_batch_iteration(a, rr, h->stream));
-        BHIP(hipEventRecord(ev.e1, h->stream));
-        BHIP(hipStreamSynchronize(h->stream));
-        float ms = 0.0f;
-        BHIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
-        if (ms < best) {
-            best = ms;
-            bo = order;
+    int bo = 1, bg = 1;
+    for (int G : {1, 2, 4}) {
+        if (G > std::min(KB, kMaxGroups)) continue;
+        for (int order : {1, 0, 3, 2}) {
+            h->order = order;
+            BHIP(launch_batch_init(h->z0, h->z[0], h->l[0], h->LP, h->Kp, h->ctrl, kMaxGroups, h->state, h->K,
+                                   1LL << 40, h->stream));
+            int rc = 0;
+            for (int phase = 0; phase < 2; ++phase) {
+                if (phase == 1) BHIP(hipEventRecord(ev.e0, h->stream));
+                if ((rc = fork_groups(h, G))) return rc;
+                for (int g = 0; g < G; ++g) {
+                    BatchArgs a;
+                    BatchRedArgs rr;
+                    int kn = 0;
+                    group_args(h, g, G, a, rr, &kn);
+                    for (int i = 0; i < (phase ? 64 : 8); ++i) BHIP(launch_batch_iteration(a, rr, kn, h->streams[g]));
+                }
+                if ((rc = join_groups(h, G))) return rc;
+            }
+            BHIP(hipEventRecord(ev.e1, h->stream));
+            BHIP(hipStreamSynchronize(h->stream));
+            float ms = 0.0f;
+            BHIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+            if (ms < best) {
+                best = ms;
+                bo = order;
+                bg = G;
+            }
         }
     }
     h->order = bo;
-    tune_cache_put(key, {bo});
+    h->groups = bg;
+    tune_cache_put(key, {bo, bg});
     return 0;
 }
 
@@ -305,8 +368,18 @@ int opf_admm_setup_batch_ex(const opf_problem* p, const double* b_scen, int32_t 
     if (h->user_stream) h->stream = h->user_stream;
     else if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
         return fail(berr(h, OPF_EHIP, "hipStreamCreate failed"));
-    if (hipHostMalloc((void**)&h->ctrl_host, sizeof(BatchCtrl), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void**)&h->ctrl_host, sizeof(BatchCtrl) * kMaxGroups, hipHostMallocDefault) != hipSuccess)
         return fail(berr(h, OPF_ENOMEM, "hipHostMalloc failed"));
+    // streams of the scenario groups (default priority) and their fork / join events
+    h->streams[0] = h->stream;
+    for (int g = 1; g < std::min(h->Kp / 64, kMaxGroups); ++g)
+        if (hipStreamCreateWithFlags(&h->streams[g], hipStreamNonBlocking) != hipSuccess)
+            return fail(berr(h, OPF_EHIP, "hipStreamCreate failed"));
+    if (hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess)
+        return fail(berr(h, OPF_EHIP, "hipEventCreate failed"));
+    for (int g = 1; g < kMaxGroups; ++g)
+        if (hipEventCreateWithFlags(&h->join[g], hipEventDisableTiming) != hipSuccess)
+            return fail(berr(h, OPF_EHIP, "hipEventCreate failed"));
     const HostLayout& L = h->lay;
     std::vector<uint16_t> planes;
     build_dense_planes(L, h->terms, planes);
@@ -361,7 +434,7 @@ int opf_admm_setup_batch_ex(const opf_problem* p, const double* b_scen, int32_t 
             return fail(berr(h, OPF_EHIP, "memset"));
     }
     if ((rc = balloc(h, &h->part, (size_t)5 * h->Kp * L.waves))) return fail(rc);
-    if ((rc = balloc(h, &h->ctrl, 1))) return fail(rc);
+    if ((rc = balloc(h, &h->ctrl, kMaxGroups))) return fail(rc);
     if ((rc = balloc(h, &h->state, K))) return fail(rc);
     if ((rc = balloc(h, &h->iters, K))) return fail(rc);
     if ((rc = balloc(h, &h->res, (size_t)4 * K))) return fail(rc);
@@ -378,36 +451,60 @@ int opf_admm_solve_batch(opf_admm_batch* h, opf_batch_result* r) {
     if (!h || !r || !r->x) return berr(h, OPF_EINVAL, "null handle, result or x");
     auto t0 = std::chrono::steady_clock::now();
     if (h->user_stream != h->stream && h->user_stream) BHIP(hipStreamSynchronize(h->user_stream));
-    BHIP(launch_batch_init(h->z0, h->z[0], h->l[0], h->LP, h->Kp, h->ctrl, h->state, h->K, h->opt.max_iter,
-                           h->stream));
+    const int G = h->groups;
     const int k = std::max(1, h->opt.check_every);
-    if (!h->graph || h->graph_k != k) {
-        if (h->graph) { (void)hipGraphExecDestroy(h->graph); h->graph = nullptr; }
-        BatchArgs a;
-        BatchRedArgs rr;
-        args_of(h, a, rr);
-        hipGraph_t g = nullptr;
-        BHIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < k; ++i) {
-            hipError_t e = launch_batch_iteration(a, rr, h->stream);
-            if (e != hipSuccess) {
-                (void)hipStreamEndCapture(h->stream, &g);
-                if (g) (void)hipGraphDestroy(g);
-                return berr(h, OPF_EHIP, std::string("launch during capture: ") + hipGetErrorString(e));
+    // one graph of k iterations per group, captured on the group's stream
+    if (h->graph_k != k || h->graph_groups != G || h->graph_order != h->order) {
+        for (auto& gr : h->graph)
+            if (gr) { (void)hipGraphExecDestroy(gr); gr = nullptr; }
+        for (int g = 0; g < G; ++g) {
+            BatchArgs a;
+            BatchRedArgs rr;
+            int kn = 0;
+            group_args(h, g, G, a, rr, &kn);
+            hipGraph_t gph = nullptr;
+            BHIP(hipStreamBeginCapture(h->streams[g], hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < k; ++i) {
+                hipError_t e = launch_batch_iteration(a, rr, kn, h->streams[g]);
+                if (e != hipSuccess) {
+                    (void)hipStreamEndCapture(h->streams[g], &gph);
+                    if (gph) (void)hipGraphDestroy(gph);
+                    return berr(h, OPF_EHIP, std::string("launch during capture: ") + hipGetErrorString(e));
+                }
+            }
+            BHIP(hipStreamEndCapture(h->streams[g], &gph));
+            hipError_t e = hipGraphInstantiate(&h->graph[g], gph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gph);
+            if (e != hipSuccess) return berr(h, OPF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        h->graph_k = k;
+        h->graph_groups = G;
+        h->graph_order = h->order;
+    }
+    BHIP(launch_batch_init(h->z0, h->z[0], h->l[0], h->LP, h->Kp, h->ctrl, G, h->state, h->K, h->opt.max_iter,
+                           h->stream));
+    int rc = fork_groups(h, G);
+    if (rc) return rc;
+    bool stopped[kMaxGroups] = {};
+    for (int left = G; left > 0;) {
+        for (int g = 0; g < G; ++g) {
+            if (stopped[g]) continue;
+            BHIP(hipGraphLaunch(h->graph[g], h->streams[g]));
+            BHIP(hipMemcpyAsync(h->ctrl_host + g, h->ctrl + g, sizeof(BatchCtrl), hipMemcpyDeviceToHost,
+                                h->streams[g]));
+        }
+        for (int g = 0; g < G; ++g) {
+            if (stopped[g]) continue;
+            BHIP(hipStreamSynchronize(h->streams[g]));
+            if (h->ctrl_host[g].stop) {
+                stopped[g] = true;
+                --left;
             }
         }
-        BHIP(hipStreamEndCapture(h->stream, &g));
-        hipError_t e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return berr(h, OPF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-        h->graph_k = k;
     }
-    for (;;) {
-        BHIP(hipGraphLaunch(h->graph, h->stream));
-        BHIP(hipMemcpyAsync(h->ctrl_host, h->ctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, h->stream));
-        BHIP(hipStreamSynchronize(h->stream));
-        if (h->ctrl_host->stop) break;
-    }
+    if ((rc = join_groups(h, G))) return rc;
+    long long total = 0;
+    for (int g = 0; g < G; ++g) total = std::max(total, (long long)h->ctrl_host[g].iter);
     const int K = h->K, n = h->lay.n;
     std::vector<int> st(K);
     std::vector<long long> it(K);
@@ -433,7 +530,7 @@ int opf_admm_solve_batch(opf_admm_batch* h, opf_batch_result* r) {
         if (r->eps_prim) r->eps_prim[q] = res[(size_t)4 * q + 2];
         if (r->eps_dual) r->eps_dual[q] = res[(size_t)4 * q + 3];
     }
-    r->total_iterations = h->ctrl_host->iter;
+    r->total_iterations = total;
     r->converged = converged;
     r->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (status == OPF_ENUMERIC) berr(h, OPF_ENUMERIC, "NaN/Inf in the residuals of a scenario");
@@ -458,15 +555,24 @@ int opf_admm_batch_info(const opf_admm_batch* h, opf_admm_info* info) {
     info->block_waves = 4;
     info->kernel = OPF_KERNEL_STEP;
     info->batch_order = h->order;
+    info->batch_groups = h->groups;
     return 0;
 }
 
 void opf_admm_destroy_batch(opf_admm_batch* h) {
     if (!h) return;
+    for (int g = 0; g < kMaxGroups; ++g)
+        if (h->streams[g]) (void)hipStreamSynchronize(h->streams[g]);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    for (auto& gr : h->graph)
+        if (gr) (void)hipGraphExecDestroy(gr);
     for (void* p : h->bufs) (void)hipFree(p);
     if (h->ctrl_host) (void)hipHostFree(h->ctrl_host);
+    for (int g = 1; g < kMaxGroups; ++g) {
+        if (h->streams[g]) (void)hipStreamDestroy(h->streams[g]);
+        if (h->join[g]) (void)hipEventDestroy(h->join[g]);
+    }
+    if (h->fork) (void)hipEventDestroy(h->fork);
     if (h->stream && h->stream != h->user_stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }

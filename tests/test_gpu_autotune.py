@@ -46,9 +46,10 @@ def test_batch_orders_and_autotune_cache(tmp_path, monkeypatch):
     assert np.array_equal(tuned["x"], ref["x"]) and np.array_equal(tuned["iterations"], ref["iterations"])
 
 
-@pytest.mark.parametrize("order", [0, 1, 2, 3])
-def test_each_batch_order_gives_the_same_bits(tmp_path, monkeypatch, order):
-    # a cache file holding the order forces it
+@pytest.mark.parametrize("order,groups", [(0, 1), (1, 1), (2, 1), (3, 1), (1, 2), (3, 2)])
+def test_each_batch_order_gives_the_same_bits(tmp_path, monkeypatch, order, groups):
+    # a cache file holding the order and the number of scenario groups forces them
+    # (70 scenarios: two 64-scenario chunks, the second with 6 scenarios)
     f = by_name("13bus", 0)
     inst = build_instance(f)
     B = scenario_rhs(inst, scenario_load_factors(f, 70, seed=5))
@@ -62,14 +63,47 @@ def test_each_batch_order_gives_the_same_bits(tmp_path, monkeypatch, order):
     _batch(inst, B, rho=100.0, eps_rel=1e-12, max_iter=40, check_every=8, autotune=True).close()
     key = [l for l in probe.read_text().splitlines() if l.startswith("batch/")][-1].split("\t")[0]
     cache = tmp_path / "tune.txt"
-    cache.write_text(f"{key}\t{order}\n")
+    cache.write_text(f"{key}\t{order} {groups}\n")
     monkeypatch.setenv("OPF_ADMM_TUNE_CACHE", str(cache))
-    _say(f"[gpu] batch order {order} vs default, 13bus K=70")
+    _say(f"[gpu] batch order {order}, {groups} scenario groups vs default, 13bus K=70")
     s = _batch(inst, B, rho=100.0, eps_rel=1e-12, max_iter=40, check_every=8, autotune=True)
-    assert s.info().batch_order == order
+    info = s.info()
+    assert (info.batch_order, info.batch_groups) == (order, groups)
     out = s.solve()
     s.close()
     assert np.array_equal(out["x"], ref["x"])
+    assert np.array_equal(out["iterations"], ref["iterations"])
+
+
+@pytest.mark.parametrize("groups", [2, 4])
+def test_scenario_groups_solve_to_tolerance_with_the_same_bits(tmp_path, monkeypatch, groups):
+    """Four 64-scenario chunks of the 123-bus feeder iterated as 2 or 4 groups
+    on concurrent streams: every scenario stops at the same iteration with the
+    same solution as in one group (scenarios are independent), and the batch
+    runs until the last group has stopped."""
+    f = by_name("123bus", 0)
+    inst = build_instance(f)
+    B = scenario_rhs(inst, scenario_load_factors(f, 256, seed=7))
+    s = _batch(inst, B, rho=100.0, eps_rel=1e-3, check_every=64)
+    ref = s.solve()
+    s.close()
+    probe = tmp_path / "probe.txt"
+    monkeypatch.setenv("OPF_ADMM_TUNE_CACHE", str(probe))
+    _batch(inst, B, rho=100.0, eps_rel=1e-3, check_every=64, autotune=True).close()
+    key = [l for l in probe.read_text().splitlines() if l.startswith("batch/")][-1].split("\t")[0]
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{key}\t1 {groups}\n")
+    monkeypatch.setenv("OPF_ADMM_TUNE_CACHE", str(cache))
+    _say(f"[gpu] 123bus K=256 to 1e-3: {groups} scenario groups vs one")
+    s = _batch(inst, B, rho=100.0, eps_rel=1e-3, check_every=64, autotune=True)
+    assert s.info().batch_groups == groups
+    out = s.solve()
+    s.close()
+    assert ref["converged"] == 256 and out["converged"] == 256
+    assert np.array_equal(out["iterations"], ref["iterations"])
+    assert np.array_equal(out["x"], ref["x"])
+    assert np.array_equal(out["objective"], ref["objective"])
+    assert out["total_iterations"] >= int(out["iterations"].max())
 
 
 def test_single_instance_autotune_cache(tmp_path, monkeypatch):
