@@ -28,8 +28,17 @@
  *   - calls on one handle are not thread-safe; distinct handles are
  *     independent;
  *   - return value: 0 on success, OPF_NOT_CONVERGED (a warning, +1) when
- *     max_iter was reached, a negative OPF_E* code on error.  The message of
- *     the last error is available from opf_admm_last_error.
+ *     max_iter was reached, OPF_STALLED (+2) when the optional stall watch
+ *     ended the solve, a negative OPF_E* code on error.  The message of the
+ *     last error is available from opf_admm_last_error.
+ *
+ * Metrics records: when the environment variable OPF_ADMM_METRICS names a
+ * file, opf_admm_solve, opf_admm_run_fixed, opf_admm_solve_batch and every
+ * served request append one JSON object per solve as a line of it (sizes,
+ * schedule, status, iterations, residuals, wall and kernel times, iteration
+ * rate, algorithmic bytes per iteration and their effective rate, and up to
+ * 64 (pres, dres) pairs of the residual history when one is kept).
+ * opf_admm_solve_noalloc writes none.
  */
 #ifndef OPF_ADMM_H
 #define OPF_ADMM_H
@@ -43,6 +52,9 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------ */
 #define OPF_OK                     0
 #define OPF_NOT_CONVERGED          1   /* max_iter reached; outputs hold the last iterate */
+#define OPF_STALLED                2   /* the stall watch (opf_admm_options.stall_window) saw the residual
+                                          merit stop falling: the problem is likely infeasible; outputs
+                                          hold the last iterate */
 #define OPF_EINVAL                (-1) /* bad sizes, NaN/Inf in A, b or c, index out of range, duplicate index in one B_s */
 #define OPF_EBOUNDS               (-2) /* lb > ub or NaN bound */
 #define OPF_EUNCOVERED            (-3) /* a global variable has no local copy: B^T B singular (Section IV-C) */
@@ -51,6 +63,7 @@ extern "C" {
 #define OPF_EHIP                  (-6) /* a HIP runtime call failed */
 #define OPF_ENUMERIC              (-7) /* NaN/Inf appeared in the residuals */
 #define OPF_EHANG                 (-8) /* a bounded device-side wait ran out (persistent kernel) */
+#define OPF_ECANCELED             (-9) /* serving: the request was cancelled (opf_server_cancel) */
 
 /* ---- precision of the iteration ----------------------------------------- */
 #define OPF_PREC_FP64   0   /* factors, state, residuals all FP64 */
@@ -172,6 +185,23 @@ typedef struct opf_admm_options {
     int32_t tiled_workgroups; /* TILED: compute workgroups of the launch (0 = the fewest that hold every
                                tile with an even share, limited by what the device holds at once);
                                fewer workgroups take more tiles each */
+    /* Stall watch of the FP64 iterations (FP64 solves and the polish phase of
+       mixed solves; not with fixed iteration counts).  The merit
+       pres^2 + (dres / rho)^2 of the termination test's residuals
+       (Section III-C) does not increase from iteration to iteration, and
+       falls to 0 when the problem is feasible; on an infeasible one (each
+       component's equations solvable, their consensus not) it settles at a
+       positive plateau.  With stall_window > 0 the iterations run in windows
+       of that many; after each window the merit of its last iteration is
+       compared with the previous window's, and after stall_checks windows in
+       a row in which it fell by less than the fraction stall_delta the solve
+       stops with OPF_STALLED.  Windows change no arithmetic: a solve that is
+       not stopped returns the same bits.  0 fields take defaults when
+       stall_window > 0: stall_checks 3, stall_delta 1e-3. */
+    int64_t stall_window;
+    double  stall_delta;    /* in (0, 1) */
+    int32_t stall_checks;   /* >= 1 */
+    int32_t reserved_stall;
 } opf_admm_options;
 
 #define OPF_RHO_RELATIVE 0
@@ -470,6 +500,15 @@ int opf_server_create(const opf_server_options* o, void* hip_stream, opf_server*
  */
 int opf_server_submit(opf_server* s, const opf_problem* p, uint64_t family, const uint64_t* comp_keys,
                       double* x_out, int64_t* request_id);
+
+/* Cancels a submitted request that has not been answered yet.  A request
+ * still queued (in set-up or waiting for admission) is answered at once; one
+ * in set-up when set-up ends; a resident one before the next shared round, with
+ * its current iterate in x_out (iterations and residuals of its last completed
+ * round).  Its result, polled as usual, has status OPF_ECANCELED, and no
+ * warm-start state is kept from it.  Returns 0, or OPF_EINVAL for an unknown
+ * or already answered request id. */
+int opf_server_cancel(opf_server* s, int64_t request_id);
 
 /* Moves up to max_out finished results into out (waiting up to wait_ms for
    the first); returns how many were written. */

@@ -60,3 +60,16 @@ def random_instance(seed: int = 0, n: int = 400) -> Instance:
     lb[one] = xstar[one] - 1.0
     return Instance(name=f"random-lp-{seed}", n=n, c=c, lb=lb, ub=ub, var_kind=kind,
                     var_keys=[None] * n, comps=comps)
+
+
+def inconsistent_instance(seed: int = 0, n: int = 120) -> Instance:
+    """A random feasible LP with two more one-slot components that fix
+    variable 0 to +0.5 and to -0.5: every component's equations are
+    solvable, their consensus is not (an infeasible LP for the stall watch)."""
+    base = random_instance(seed, n)
+    comps = list(base.comps)
+    for v in (0.5, -0.5):
+        comps.append(Component(kind="random", ident=("pin", v), A=np.ones((1, 1)), b=np.array([v]),
+                               idx=np.array([0], dtype=np.int64)))
+    return Instance(name=f"inconsistent-lp-{seed}", n=n, c=base.c, lb=base.lb, ub=base.ub,
+                    var_kind=base.var_kind, var_keys=[None] * n, comps=comps)

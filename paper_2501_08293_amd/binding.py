@@ -27,6 +27,8 @@ OPF_ENOMEM = -5
 OPF_EHIP = -6
 OPF_ENUMERIC = -7
 OPF_EHANG = -8
+OPF_ECANCELED = -9
+OPF_STALLED = 2
 
 OPF_PREC_FP64 = 0
 OPF_PREC_MIXED = 1
@@ -43,14 +45,15 @@ OPF_RHO_LAG = 4
 OPF_ADMIT_LARGEST_FIRST = 0
 OPF_ADMIT_ARRIVAL = 1
 
-STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBOUNDS", -3: "EUNCOVERED",
-                -4: "EINFEASIBLE_COMPONENT", -5: "ENOMEM", -6: "EHIP", -7: "ENUMERIC", -8: "EHANG"}
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "STALLED", -1: "EINVAL", -2: "EBOUNDS", -3: "EUNCOVERED",
+                -4: "EINFEASIBLE_COMPONENT", -5: "ENOMEM", -6: "EHIP", -7: "ENUMERIC", -8: "EHANG",
+                -9: "ECANCELED"}
 
 EXPORTED = ["opf_admm_default_options", "opf_admm_setup", "opf_admm_solve", "opf_admm_run_fixed",
             "opf_admm_solve_noalloc",
             "opf_admm_residuals", "opf_admm_get_info", "opf_admm_destroy", "opf_admm_last_error",
             "opf_admm_setup_batch", "opf_admm_setup_batch_ex", "opf_admm_solve_batch", "opf_admm_batch_info", "opf_admm_destroy_batch",
-            "opf_admm_batch_last_error", "opf_server_default_options", "opf_server_create", "opf_server_submit",
+            "opf_admm_batch_last_error", "opf_server_default_options", "opf_server_create", "opf_server_submit", "opf_server_cancel",
             "opf_server_poll", "opf_server_get_stats", "opf_server_destroy", "opf_server_last_error"]
 
 
@@ -69,7 +72,9 @@ class opf_admm_options(C.Structure):
                 ("spin_limit", C.c_int32), ("split_terms", C.c_int32), ("autotune", C.c_int32),
                 ("workgroup_order", C.c_int32), ("setup_on_device", C.c_int32), ("rho_every", C.c_int32),
                 ("rho_mode", C.c_int32), ("rho_mu", C.c_double), ("rho_tau", C.c_double), ("rho_min", C.c_double),
-                ("rho_max", C.c_double), ("local_updates", C.c_int32), ("tiled_workgroups", C.c_int32)]
+                ("rho_max", C.c_double), ("local_updates", C.c_int32), ("tiled_workgroups", C.c_int32),
+                ("stall_window", C.c_int64), ("stall_delta", C.c_double), ("stall_checks", C.c_int32),
+                ("reserved_stall", C.c_int32)]
 
 
 class opf_warm(C.Structure):
@@ -206,6 +211,8 @@ def load(path: str = LIB_PATH):
     lib.opf_server_submit.restype = C.c_int
     lib.opf_server_poll.argtypes = [H, C.POINTER(opf_served), C.c_int, C.c_int]
     lib.opf_server_poll.restype = C.c_int
+    lib.opf_server_cancel.argtypes = [H, C.c_int64]
+    lib.opf_server_cancel.restype = C.c_int
     lib.opf_server_get_stats.argtypes = [H, C.POINTER(opf_server_stats)]
     lib.opf_server_get_stats.restype = C.c_int
     lib.opf_server_destroy.argtypes = [H]
@@ -419,7 +426,8 @@ class Solver:
                  eps_rel=1e-3, max_iter=1_000_000, precision=OPF_PREC_FP64, polish=True, check_every=256,
                  kernel=OPF_KERNEL_AUTO, history_cap=0, block_waves=0, spin_limit=0, autotune=False,
                  workgroup_order=0, setup_on_device=False, rho_every=0, rho_mode=OPF_RHO_RELATIVE, rho_mu=0.0,
-                 rho_tau=0.0, rho_min=0.0, rho_max=0.0, local_updates=1, tiled_workgroups=0, stream=0):
+                 rho_tau=0.0, rho_min=0.0, rho_max=0.0, local_updates=1, tiled_workgroups=0, stall_window=0,
+                 stall_checks=0, stall_delta=0.0, stream=0):
         self._keep = dict(
             c=np.ascontiguousarray(c, np.float64), lb=np.ascontiguousarray(lb, np.float64),
             ub=np.ascontiguousarray(ub, np.float64), var_kind=np.ascontiguousarray(var_kind, np.uint8),
@@ -456,6 +464,9 @@ class Solver:
         o.rho_max = rho_max
         o.local_updates = local_updates
         o.tiled_workgroups = tiled_workgroups
+        o.stall_window = stall_window
+        o.stall_checks = stall_checks
+        o.stall_delta = stall_delta
         self.options = o
         self.h = opf_admm_setup(p, o, stream)
         self._keep = None   # the library copied everything it needs
@@ -599,6 +610,12 @@ class Server:
             raise OpfError(rc, load().opf_server_last_error(self.h).decode())
         self._pending[rid.value] = x
         return rid.value
+
+    def cancel(self, request_id) -> None:
+        """Cancels an unanswered request; its result (status OPF_ECANCELED) comes through poll."""
+        rc = load().opf_server_cancel(self.h, C.c_int64(int(request_id)))
+        if rc != OPF_OK:
+            raise OpfError(rc, load().opf_server_last_error(self.h).decode())
 
     def poll(self, max_out=64, wait_ms=0):
         buf = (opf_served * max_out)()

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libopf_admm.so")
-SOURCES = ["setup.cpp", "tune_cache.cpp", "setup_device.hip", "admm_step.hip", "admm_persistent.hip", "admm_tiled.hip", "admm_batch.hip", "admm_multi.hip", "api.hip", "api_batch.hip",
+SOURCES = ["setup.cpp", "tune_cache.cpp", "metrics.cpp", "setup_device.hip", "admm_step.hip", "admm_persistent.hip", "admm_tiled.hip", "admm_batch.hip", "admm_multi.hip", "api.hip", "api_batch.hip",
            "api_server.hip"]
 ARCH = os.environ.get("OPF_OFFLOAD_ARCH", "gfx950")
 

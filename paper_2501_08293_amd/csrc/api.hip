@@ -15,6 +15,7 @@
 #include "../../include/opf_admm.h"
 #include "admm_kernels.h"
 #include "setup_device.h"
+#include "metrics.h"
 #include "tune_cache.h"
 #include "opf_layout.h"
 
@@ -465,6 +466,78 @@ int prepare_start(opf_admm_handle* h, const opf_warm* warm, const double** z0, c
     return 0;
 }
 
+// The metrics record of one solve (OPF_ADMM_METRICS): sizes, schedule,
+// status, iterations, residuals, times, the iteration rate and the effective
+// rate of the algorithmic bytes of the bulk precision; with a residual history
+// on the device, up to 64 evenly spaced (pres, dres) pairs of it.
+void record_solve(opf_admm_handle* h, const opf_result* r, const char* kind) {
+    const HostLayout& L = h->lay;
+    const bool mixed = h->opt.precision == OPF_PREC_MIXED;
+    const double e = mixed ? 4.0 : 8.0;
+    const double bytes = e * (double)L.sum_ns2 + (7 * e + 8) * (double)L.L + (4 * e + 4) * (double)L.n;
+    const long long it_bulk = mixed ? r->iterations_fp32 : r->iterations;
+    const double ms_bulk = mixed ? r->kernel_ms_fp32 : r->kernel_ms;
+    static const char* kname[] = {"auto", "step", "persistent", "tiled"};
+    JsonLine j;
+    j.str("kind", kind).integer("n", L.n).integer("S", L.S).integer("L", L.L)
+        .str("precision", mixed ? "mixed" : "fp64").str("kernel", kname[std::min(std::max(h->kernel, 0), 3)])
+        .integer("block_waves", h->wpb).integer("status", r->status).integer("iterations", r->iterations)
+        .integer("iterations_fp32", r->iterations_fp32).num("objective", r->objective).num("pres", r->pres)
+        .num("dres", r->dres).num("eps_prim", r->eps_prim).num("eps_dual", r->eps_dual)
+        .num("rho_final", r->rho_final).num("solve_ms", r->solve_ms).num("kernel_ms", r->kernel_ms)
+        .num("iters_per_s", r->solve_ms > 0 ? 1e3 * (double)r->iterations / r->solve_ms : 0.0)
+        .num("bytes_per_iteration", bytes)
+        .num("effective_gbs", ms_bulk > 0 ? bytes * (double)it_bulk / (ms_bulk * 1e-3) / 1e9 : 0.0);
+    const long long rows = std::min<long long>(h->opt.history_cap, r->iterations);
+    if (rows > 0) {
+        std::vector<double> hb((size_t)rows * 4);
+        if (hipMemcpyAsync(hb.data(), h->hist, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, h->stream) ==
+                hipSuccess && hipStreamSynchronize(h->stream) == hipSuccess) {
+            std::vector<std::pair<double, double>> hs;
+            const long long step = std::max<long long>(1, (rows + 63) / 64);
+            for (long long u = 0; u < rows; u += step) hs.push_back({hb[(size_t)u * 4], hb[(size_t)u * 4 + 1]});
+            j.integer("history_every", step).pairs("history", hs);
+        }
+    }
+    metrics_write(j);
+}
+
+// FP64 iterations up to the absolute cap `cap` (the control block already
+// armed for them), with the stall watch when it is on: windows of
+// stall_window iterations, the merit pres^2 + (dres / rho)^2 of each
+// window's last iteration against the previous one.  Sets *status.
+int run_fp64_watched(opf_admm_handle* h, long long cap, const Work& w, int* status) {
+    const long long W = h->opt.stall_window;
+    if (W <= 0) {
+        int rc = run_any<double>(h, h->s64, &h->graph64, cap, 1, w);
+        if (rc) return rc;
+        *status = h->ctrl_host->status;
+        return 0;
+    }
+    long long stop_at = std::min<long long>(h->ctrl_host->iter + W, cap);
+    HIPCHK(launch_rearm(h->ctrl, stop_at, 1, h->stream));
+    int rc = run_any<double>(h, h->s64, &h->graph64, stop_at, 1, w);
+    if (rc) return rc;
+    double m_prev = HUGE_VAL;
+    int flat = 0;
+    while (h->ctrl_host->status == OPF_NOT_CONVERGED && h->ctrl_host->iter < cap) {
+        const Ctrl& c = *h->ctrl_host;
+        const double rho_t = h->opt.rho_every ? c.rho[c.iter % kRhoRing] : h->opt.rho;
+        const double m = c.res[0] * c.res[0] + (c.res[1] / rho_t) * (c.res[1] / rho_t);
+        flat = m > (1.0 - h->opt.stall_delta) * m_prev ? flat + 1 : 0;
+        m_prev = m;
+        if (flat >= h->opt.stall_checks) {
+            *status = OPF_STALLED;
+            return 0;
+        }
+        stop_at = std::min<long long>(c.iter + W, cap);
+        HIPCHK(launch_rearm(h->ctrl, stop_at, 1, h->stream));
+        if ((rc = run_any<double>(h, h->s64, &h->graph64, stop_at, 1, w))) return rc;
+    }
+    *status = h->ctrl_host->status;
+    return 0;
+}
+
 int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long long fixed_iters, const Work& w) {
     if (!h || !r || !r->x) return set_err(h, OPF_EINVAL, "null handle, result or x");
     auto t0 = std::chrono::steady_clock::now();
@@ -510,18 +583,19 @@ int solve_impl(opf_admm_handle* h, const opf_warm* warm, opf_result* r, long lon
         if (polish) {
             HIPCHK(launch_promote(h->s32.z[0], h->s32.z[1], h->s32.l[0], h->s32.l[1], h->s64.z[0], h->s64.z[1],
                                   h->s64.l[0], h->s64.l[1], h->LP, h->ctrl, it32 + h->opt.max_iter, 1, h->stream));
-            rc = run_any<double>(h, h->s64, &h->graph64, it32 + h->opt.max_iter, 1, w);
-            if (rc) return rc;
-            status = h->ctrl_host->status;
+            if ((rc = run_fp64_watched(h, it32 + h->opt.max_iter, w, &status))) return rc;
         } else {
             final64 = false;
         }
     } else {
         HIPCHK(launch_init<double>(z0, l0, h->s64.z[0], h->s64.l[0], h->LP, h->ctrl, max_iter, check, h->opt.rho,
                                    h->stream));
-        rc = run_any<double>(h, h->s64, &h->graph64, max_iter, check, w);
-        if (rc) return rc;
-        status = h->ctrl_host->status;
+        if (fixed) {
+            if ((rc = run_any<double>(h, h->s64, &h->graph64, max_iter, check, w))) return rc;
+            status = h->ctrl_host->status;
+        } else if ((rc = run_fp64_watched(h, max_iter, w, &status))) {
+            return rc;
+        }
     }
     rc = final64 ? finish_outputs<double>(h, h->s64, r) : finish_outputs<float>(h, h->s32, r);
     if (rc) return rc;
@@ -742,6 +816,12 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
         return set_err(nullptr, OPF_EINVAL, "unknown precision");
     if (opt.history_cap < 0) return set_err(nullptr, OPF_EINVAL, "history_cap must be >= 0");
     if (opt.rho_every < 0) return set_err(nullptr, OPF_EINVAL, "rho_every must be >= 0");
+    if (opt.stall_window < 0 || opt.stall_checks < 0 || opt.stall_delta < 0 || opt.stall_delta >= 1)
+        return set_err(nullptr, OPF_EINVAL, "stall watch: window, checks >= 0 and delta in [0, 1)");
+    if (opt.stall_window > 0) {
+        if (opt.stall_checks == 0) opt.stall_checks = 3;
+        if (opt.stall_delta == 0) opt.stall_delta = 1e-3;
+    }
     if (opt.local_updates < 0) return set_err(nullptr, OPF_EINVAL, "local_updates must be >= 0");
     if (opt.local_updates == 0) opt.local_updates = 1;
     if (opt.rho_every > 0) {
@@ -901,13 +981,17 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
 
 int opf_admm_solve(opf_admm_handle* h, const opf_warm* warm, opf_result* r) {
     if (!h) return set_err(nullptr, OPF_EINVAL, "null handle");
-    return solve_impl(h, warm, r, 0, h->work);
+    const int rc = solve_impl(h, warm, r, 0, h->work);
+    if ((rc >= 0 || rc == OPF_ENUMERIC) && metrics_on()) record_solve(h, r, "solve");
+    return rc;
 }
 
 int opf_admm_run_fixed(opf_admm_handle* h, const opf_warm* warm, int64_t iters, opf_result* r) {
     if (!h) return set_err(nullptr, OPF_EINVAL, "null handle");
     if (iters < 1) return set_err(h, OPF_EINVAL, "iters must be >= 1");
-    return solve_impl(h, warm, r, iters, h->work);
+    const int rc = solve_impl(h, warm, r, iters, h->work);
+    if ((rc >= 0 || rc == OPF_ENUMERIC) && metrics_on()) record_solve(h, r, "fixed");
+    return rc;
 }
 
 int opf_admm_solve_noalloc(opf_admm_handle* h, const opf_warm* warm, opf_result* r) {

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/opf_admm.h"
+#include "metrics.h"
 #include "tune_cache.h"
 #include "admm_batch.h"
 #include "admm_kernels.h"
@@ -533,6 +534,20 @@ int opf_admm_solve_batch(opf_admm_batch* h, opf_batch_result* r) {
     r->total_iterations = total;
     r->converged = converged;
     r->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (metrics_on()) {
+        // algorithmic bytes of one batch iteration: the shared FP64 factors once,
+        // and per slot and scenario (FP32 state) z and lambda read and written,
+        // the x gather and b-bar
+        const double bytes = 8.0 * (double)h->lay.sum_ns2 + 24.0 * (double)K * (double)h->lay.L;
+        JsonLine j;
+        j.str("kind", "batch").integer("n", n).integer("S", h->lay.S).integer("L", h->lay.L).integer("K", K)
+            .integer("status", status).integer("converged", converged).integer("total_iterations", total)
+            .num("solve_ms", r->solve_ms).num("us_per_iteration", total > 0 ? 1e3 * r->solve_ms / (double)total : 0.0)
+            .num("bytes_per_iteration", bytes)
+            .num("effective_gbs", r->solve_ms > 0 ? bytes * (double)total / (r->solve_ms * 1e-3) / 1e9 : 0.0)
+            .integer("order", h->order).integer("groups", G);
+        metrics_write(j);
+    }
     if (status == OPF_ENUMERIC) berr(h, OPF_ENUMERIC, "NaN/Inf in the residuals of a scenario");
     return status;
 }

@@ -19,6 +19,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -26,6 +27,7 @@
 
 #include "../../include/opf_admm.h"
 #include "admm_kernels.h"
+#include "metrics.h"
 #include "opf_layout.h"
 
 namespace opf {
@@ -224,6 +226,8 @@ struct opf_server {
     std::mutex mu;
     std::condition_variable cv_setup, cv_work, cv_result;
     std::deque<std::unique_ptr<Request>> submitted, ready;
+    std::set<int64_t> live;                // submitted and not yet answered
+    std::set<int64_t> cancel;              // cancellations of requests in set-up or resident
     std::deque<opf_served> results;
     std::map<uint64_t, WarmState> warm;
     size_t warm_used = 0;
@@ -274,9 +278,20 @@ void push_result(opf_server* s, Request& r, int status, const Ctrl* c, int warm_
         for (int i = 0; i < r.n; ++i) obj += r.c[i] * r.x_out[i];
         o.objective = obj;
     }
+    if (metrics_on()) {
+        JsonLine j;
+        j.str("kind", "served").integer("request_id", o.request_id).integer("family", (long long)r.family)
+            .integer("n", r.n).integer("S", r.S).integer("status", status).integer("warm_components", warm_comps)
+            .integer("iterations", o.iterations).integer("iterations_fp32", o.iterations_fp32)
+            .num("objective", o.objective).num("pres", o.pres).num("dres", o.dres).num("eps_prim", o.eps_prim)
+            .num("eps_dual", o.eps_dual).num("queue_ms", o.queue_ms).num("latency_ms", o.latency_ms);
+        metrics_write(j);
+    }
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->results.push_back(o);
+        s->live.erase(r.id);
+        s->cancel.erase(r.id);
         if (status < 0) s->n_rejected++;
         else s->n_completed++;
     }
@@ -342,9 +357,15 @@ void setup_loop(opf_server* s) {
             push_result(s, *r, r->rc, nullptr, 0);
             continue;
         }
+        bool cancelled;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            s->ready.push_back(std::move(r));
+            cancelled = s->cancel.count(r->id) > 0;
+            if (!cancelled) s->ready.push_back(std::move(r));
+        }
+        if (cancelled) {
+            push_result(s, *r, OPF_ECANCELED, nullptr, 0);
+            continue;
         }
         s->cv_work.notify_all();
     }
@@ -460,6 +481,7 @@ int admit_one(opf_server* s, std::unique_ptr<Request>& r, int slot_id) {
     SHIPI(launch_to_device_order(zu, lu, D.user_slot, D.lanes, reinterpret_cast<const double*>(base + im.zdef),
                                 D.z0, D.l0, warm_comps > 0 ? 1 : 0, s->stream));
     SHIPI(launch_multi_init(s->d_descs, slot_id, D.lanes, s->opt.admm.max_iter, s->mixed ? 1 : 0, s->stream));
+    s->h_ctrls[slot_id] = Ctrl{};              // no round has run for this solve yet
     sl.used = true;
     sl.off = off;
     sl.len = q.img.total;
@@ -565,7 +587,8 @@ bool retire(opf_server* s, int slot_id) {
     ws.L = L.L;
     double* zo = reinterpret_cast<double*>(base + q.img.zu);
     double* lo = reinterpret_cast<double*>(base + q.img.lu);
-    bool keep = s->opt.warm_start && !q.keys.empty() && 16 * (size_t)L.L <= (size_t)s->opt.warm_bytes;
+    bool keep = s->opt.warm_start && !q.keys.empty() && c.status >= 0 &&
+                16 * (size_t)L.L <= (size_t)s->opt.warm_bytes;
     if (keep) {
         auto old = s->warm.find(q.family);
         if (old != s->warm.end()) {
@@ -666,6 +689,18 @@ void worker_loop(opf_server* s) {
     for (;;) {
         if (s->quit.load()) return;
         admit_ready(s);
+        // cancelled resident solves end before the round with their current iterate
+        std::vector<int64_t> cids;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            cids.assign(s->cancel.begin(), s->cancel.end());
+        }
+        for (int q = 0; q < (int)s->slots.size() && !cids.empty(); ++q) {
+            Slot& sl = s->slots[q];
+            if (!sl.used || !std::binary_search(cids.begin(), cids.end(), sl.req->id)) continue;
+            s->h_ctrls[q].status = OPF_ECANCELED;
+            if (!retire(s, q)) return;
+        }
         if (s->active == 0) {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait_for(lk, std::chrono::milliseconds(2),
@@ -833,10 +868,32 @@ int opf_server_submit(opf_server* s, const opf_problem* p, uint64_t family, cons
         std::lock_guard<std::mutex> lk(s->mu);
         r->id = s->next_id++;
         if (request_id) *request_id = r->id;
+        s->live.insert(r->id);
         s->n_submitted++;
         s->submitted.push_back(std::move(r));
     }
     s->cv_setup.notify_one();
+    return OPF_OK;
+}
+
+int opf_server_cancel(opf_server* s, int64_t request_id) {
+    if (!s) return serr(s, OPF_EINVAL, "null server");
+    std::unique_ptr<Request> hit;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->live.count(request_id)) return serr(s, OPF_EINVAL, "unknown or already answered request");
+        for (auto* dq : {&s->submitted, &s->ready}) {
+            for (auto it = dq->begin(); it != dq->end(); ++it)
+                if ((*it)->id == request_id) {
+                    hit = std::move(*it);
+                    dq->erase(it);
+                    break;
+                }
+            if (hit) break;
+        }
+        if (!hit) s->cancel.insert(request_id);       // in set-up or resident: ended by its owner thread
+    }
+    if (hit) push_result(s, *hit, OPF_ECANCELED, nullptr, 0);
     return OPF_OK;
 }
 

@@ -32,7 +32,7 @@ def test_struct_sizes_match_header_layout():
     binding, _ = _lib()
     assert C.sizeof(binding.opf_problem) == 88
     # rho, eps_rel, max_iter; thirteen int32 fields and 4 bytes of padding; four doubles; two reserved int32
-    assert C.sizeof(binding.opf_admm_options) == 8 + 8 + 8 + 13 * 4 + 4 + 4 * 8 + 2 * 4
+    assert C.sizeof(binding.opf_admm_options) == 8 + 8 + 8 + 13 * 4 + 4 + 4 * 8 + 2 * 4 + 8 + 8 + 2 * 4
     assert C.sizeof(binding.opf_batch_result) == 8 + 4 + 4 + 7 * 8 + 8 + 4 + 4 + 8
     assert C.sizeof(binding.opf_result) == 3 * 8 + 4 + 4 + 8 + 8 + 6 * 8 + 8 + 8 + 8 + 8
 

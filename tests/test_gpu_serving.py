@@ -309,3 +309,41 @@ def test_starvation_guard_admits_a_large_solve_ahead_of_later_small_ones():
     after = sum(1 for i in later if admit[i] >= admit[bid] - 1e-3)
     _say(f"  large solve queued {res[bid]['queue_ms']:.1f} ms; {after} of 40 later small requests admitted after it")
     assert after >= 30
+
+
+def test_cancel_queued_and_resident_requests():
+    """A request waiting for admission is answered at once with OPF_ECANCELED;
+    a resident one ends before the next round with its current iterate; the
+    server keeps serving; unknown or answered ids are rejected."""
+    from paper_2501_08293_amd import OpfError, Server
+    from paper_2501_08293_amd.binding import OPF_ECANCELED, OPF_EINVAL
+    big = build_instance(by_name("123bus", 0))
+    small = build_instance(by_name("13bus", 0))
+    _say("[gpu] serving: cancel a queued and a resident request (one slot)")
+    srv = Server(rho=RHO, eps_rel=1e-12, max_iter=200_000, warm_start=False, iters_per_poll=64, max_slots=1,
+                 arena_bytes=256 << 20)
+    try:
+        a = srv.submit(*_args(big), family=1)
+        t0 = time.time()
+        while srv.stats()["resident"] < 1:
+            assert time.time() - t0 < 30
+            time.sleep(0.005)
+        b = srv.submit(*_args(small), family=2)
+        time.sleep(0.05)                       # a few rounds of the resident solve; b is set up meanwhile
+        srv.cancel(b)                          # still waiting for the only slot
+        rb = _drain(srv, [b])[b]
+        assert rb["status"] == OPF_ECANCELED and rb["iterations"] == 0
+        srv.cancel(a)
+        ra = _drain(srv, [a])[a]
+        assert ra["status"] == OPF_ECANCELED
+        assert ra["iterations"] > 0 and np.all(np.isfinite(ra["x"]))
+        with pytest.raises(OpfError) as e:
+            srv.cancel(a)                      # already answered
+        assert e.value.code == OPF_EINVAL
+        with pytest.raises(OpfError):
+            srv.cancel(10 ** 9)                # never submitted
+        c = srv.submit(*_args(small), family=3)
+        rc = _drain(srv, [c])[c]
+        assert rc["status"] in (0, 1) and rc["iterations"] > 0     # served as usual (eps 1e-12: to max_iter or converged)
+    finally:
+        srv.close()
