@@ -470,7 +470,7 @@ def zip_batch_timing(args, torch, K):
             "us_per_batch_iteration": round(1e6 * wall / max(int(out["total_iterations"]), 1), 2)}
 
 
-def serve_leg(args, torch):
+def serve_leg(args, torch, rate=None, baseline=True):
     import numpy as np
     from opfgen import build_instance, scenario_rhs
     from opfgen.serving import component_keys, make_family, poisson_arrivals, reconfigure
@@ -488,7 +488,8 @@ def serve_leg(args, torch):
     gen_s = time.perf_counter() - t0
     N = args.serve_requests
     rng = np.random.default_rng([args.seed, 808])
-    arrivals = poisson_arrivals(N, args.serve_rate, args.seed)
+    rate = args.serve_rate if rate is None else rate
+    arrivals = poisson_arrivals(N, rate, args.seed)
     reqs = []
     for k in range(N):
         fid, inst, keys = pool[int(rng.integers(len(pool)))]
@@ -517,8 +518,30 @@ def serve_leg(args, torch):
     srv.close()
     lat = np.array([done[i]["latency_ms"] for i in range(N)])
     ok = sum(1 for i in range(N) if done[i]["status"] == 0)
+    # algorithmic bytes of every served iteration (FP32 bulk and FP64 ones at
+    # their element sizes) over the served span
+    served_bytes = 0.0
+    for i in range(N):
+        inst_i, r_i = reqs[i][1], done[i]
+        s2 = sum(len(c.idx) ** 2 for c in inst_i.comps)
+        it32 = int(r_i["iterations_fp32"])
+        it64 = int(r_i["iterations"]) - it32
+        served_bytes += (algorithmic_bytes_per_iteration(s2, inst_i.L, inst_i.n, 4) * it32 +
+                         algorithmic_bytes_per_iteration(s2, inst_i.L, inst_i.n, 8) * it64)
+    served_gbs = served_bytes / span / 1e9
     warm = sum(1 for i in range(N) if done[i]["warm_components"] > 0)
-    print(f"[bench] served {N} requests in {span:.1f} s; one-at-a-time baseline next", file=sys.stderr, flush=True)
+    print(f"[bench] served {N} requests at {rate:g}/s in {span:.1f} s", file=sys.stderr, flush=True)
+    roof = {"bound": "hbm", "achieved": round(served_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(served_gbs / HBM_PEAK_GBS, 4),
+            "basis": "algorithmic bytes of every served iteration over the served span"}
+    if not baseline:
+        return {"workload": f"{N} requests, Poisson {rate:g}/s, {args.serve_families} feeder families, "
+                            f"eps_rel={args.serve_eps:g}",
+                "solves_per_s": round(ok / span, 2), "span_s": round(span, 2),
+                "p50_latency_ms": round(float(np.percentile(lat, 50)), 1),
+                "p99_latency_ms": round(float(np.percentile(lat, 99)), 1),
+                "max_latency_ms": round(float(lat.max()), 1), "converged": ok, "warm_started": warm,
+                "launches": int(sstats["launches"]), "roofline": roof}
     # baseline: the same trace served one solve at a time, FIFO, cold start,
     # with the single-instance solver (set-up included, as in the runtime)
     base_lat = []
@@ -586,6 +609,7 @@ def serve_leg(args, torch):
             "one_at_a_time_median": float(np.median(err_base)) if samp else None,
             "per_request": rows},
         "launches": int(sstats["launches"]), "generator_s": round(gen_s, 1),
+        "roofline": roof,
     }
 
 
@@ -617,6 +641,9 @@ def main():
         progress(f"batch done: {line['batch']['time_to_all_ms']} ms")
     if not args.skip_serve:
         line["serving"] = serve_leg(args, torch)
+        # the same families and request mix arriving ten times slower: admission
+        # while solves run (no one-at-a-time baseline)
+        line["serving"]["paced"] = serve_leg(args, torch, rate=args.serve_rate / 10, baseline=False)
         progress(f"serving done: {line['serving']['solves_per_s']} solves/s")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, args.eps, args.cpu_seconds, args.workload)
