@@ -454,8 +454,9 @@ def zip_batch_timing(args, torch, K):
     t0 = time.perf_counter()
     s = BatchSolver(inst.n, inst.c, inst.lb, inst.ub, inst.var_kind, *inst.flat(), b_scen=b_scen, rho=100.0,
                     eps_rel=1e-12, max_iter=2048, check_every=256, stream=st.cuda_stream, a_pos=a_pos,
-                    a_scen=a_scen)
+                    a_scen=a_scen, autotune=bool(args.autotune))
     setup_s = time.perf_counter() - t0
+    info = s.info()
     s.solve()
     t0 = time.perf_counter()
     out = s.solve()
@@ -466,7 +467,7 @@ def zip_batch_timing(args, torch, K):
     comp_of = np.searchsorted(np.cumsum(cm.astype(np.int64) * cn), a_pos, side="right")
     return {"workload": f"{inst.name}: {K} scenarios, {len(a_pos)} scenario-varying A entries in "
                         f"{len(np.unique(comp_of))} of {inst.S} components; 2048 iterations timed",
-            "setup_s": round(setup_s, 2),
+            "setup_s": round(setup_s, 2), "workgroup_order": info.batch_order, "scenario_groups": info.batch_groups,
             "us_per_batch_iteration": round(1e6 * wall / max(int(out["total_iterations"]), 1), 2)}
 
 

@@ -121,3 +121,35 @@ def test_single_instance_autotune_cache(tmp_path, monkeypatch):
     line = [l for l in txt.splitlines() if l.startswith("single/")][-1]
     k, bw = (int(v) for v in line.split("\t")[1].split())
     assert (info.kernel, info.block_waves) == (k, bw)
+
+
+def test_scenario_groups_with_zip_loads_give_the_same_bits(tmp_path, monkeypatch):
+    """ZIP loads (scenario-varying A_s in their own wavefronts, first in every
+    group's launch) with the 64-scenario chunks split over two concurrent
+    groups: each scenario gets the bits of the one-group run."""
+    from opfgen import scenario_zip
+    f = by_name("13bus-zip", 0)
+    inst = build_instance(f)
+    fac = scenario_load_factors(f, 70, seed=11)
+    b_scen, a_pos, a_scen = scenario_zip(inst, fac)
+
+    def mk(**kw):
+        return _batch(inst, b_scen, rho=100.0, eps_rel=1e-12, max_iter=60, check_every=20, a_pos=a_pos,
+                      a_scen=a_scen, **kw)
+    s = mk()
+    ref = s.solve()
+    s.close()
+    probe = tmp_path / "probe.txt"
+    monkeypatch.setenv("OPF_ADMM_TUNE_CACHE", str(probe))
+    mk(autotune=True).close()
+    key = [l for l in probe.read_text().splitlines() if l.startswith("batch/")][-1].split("\t")[0]
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{key}\t1 2\n")
+    monkeypatch.setenv("OPF_ADMM_TUNE_CACHE", str(cache))
+    _say("[gpu] 13bus-zip K=70: two scenario groups vs one")
+    s = mk(autotune=True)
+    assert s.info().batch_groups == 2
+    out = s.solve()
+    s.close()
+    assert np.array_equal(out["x"], ref["x"])
+    assert np.array_equal(out["iterations"], ref["iterations"])
