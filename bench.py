@@ -287,6 +287,7 @@ def single_instance(args, torch):
             "block_waves": info.block_waves,
             "workgroups": info.grid_blocks,
             "factors_in_lds": info.factors_in_lds,
+            "fp64_lds_workgroups": info.fp64_lds_workgroups,
             "kernel_ms_per_solve": round(sum(r["kernel_ms"] for r in results) / args.steps, 3),
             **accuracy(results[-1]["objective"], stored_reference(args.workload, args.eps)),
         },

@@ -257,7 +257,8 @@ typedef struct opf_admm_info {
     int32_t kernel;            /* OPF_KERNEL_STEP or OPF_KERNEL_PERSISTENT, as selected */
     int32_t persistent_capacity;   /* co-resident workgroups the device can hold */
     int32_t max_neighbours;    /* largest number of workgroups one workgroup waits on */
-    int32_t factors_in_lds;    /* persistent schedule: bit 0 FP32, bit 1 FP64 factors held in LDS */
+    int32_t factors_in_lds;    /* persistent schedule: bit 0 FP32 factors held in LDS (every workgroup's),
+                                  bit 1 FP64 (the workgroups whose columns fit the launch's budget) */
     int32_t batch_order;       /* batched path: workgroup order of the step kernel, bit 0 = each XCD runs
                                   a contiguous range of the packing, bit 1 = 64-scenario-chunk-major */
     int32_t tiled_pair;        /* TILED: 1 when the two-tile kernel runs (each workgroup keeps two tiles in
@@ -265,7 +266,7 @@ typedef struct opf_admm_info {
                                   bulk phase) */
     int32_t batch_groups;      /* batched path: scenario groups iterated by concurrent launches on their own
                                   streams (the 64-scenario chunks split into contiguous ranges) */
-    int32_t reserved[1];
+    int32_t fp64_lds_workgroups; /* persistent schedule: workgroups holding their FP64 factors in LDS */
 } opf_admm_info;
 
 typedef struct opf_admm_handle opf_admm_handle;

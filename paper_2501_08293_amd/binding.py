@@ -102,7 +102,7 @@ class opf_admm_info(C.Structure):
                 ("setup_ms", C.c_double), ("grid_blocks", C.c_int32), ("block_waves", C.c_int32),
                 ("kernel", C.c_int32), ("persistent_capacity", C.c_int32), ("max_neighbours", C.c_int32),
                 ("factors_in_lds", C.c_int32), ("batch_order", C.c_int32), ("tiled_pair", C.c_int32),
-                ("batch_groups", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("batch_groups", C.c_int32), ("fp64_lds_workgroups", C.c_int32)]
 
 
 class opf_batch_result(C.Structure):

@@ -181,8 +181,9 @@ struct PersistArgs {
     long long spin_limit;       // polls before a wait gives up
     long long max_iter;         // stop when this iteration count is reached
     int check;                  // 1: apply the termination test
-    int lds_factors;            // 1: factors copied once into LDS (dynamic shared memory)
-    int lds_factor_cols;        // largest sum over a workgroup's wavefronts of their factor columns
+    int lds_factors;            // 0: factors read from memory; FP32: 1 = every workgroup's factors in LDS;
+                                // FP64: the column budget (workgroups within it hold theirs in LDS)
+    int lds_factor_cols;        // columns of dynamic shared memory per workgroup
     int xcd_remap;              // 1: consecutive workgroups of the packing share an XCD
 };
 

@@ -284,11 +284,15 @@ __device__ void persistent_instance(const InstanceView<T>& a, int b, int G, int*
 }
 
 
+// FP64: each workgroup keeps its factors in LDS when their columns fit the
+// launch's column budget (p.lds_factors), so that a problem whose largest
+// workgroups would not let the grid fit still holds most of its factors in
+// LDS; FP32: all workgroups or none (every FP32 problem here fits).
 template <typename T, int WPB, bool ADAPT>
 __global__ __launch_bounds__(WPB * 64) void admm_persistent_kernel(IterArgs<T> a, PersistArgs p) {
     const InstanceView<T> v = view_of(a, p);
     const int b = logical_block((int)blockIdx.x, (int)gridDim.x, p.xcd_remap);
-    persistent_instance<T, WPB, false, ADAPT>(v, b, (int)gridDim.x - 1, p.error, p.spin_limit);
+    persistent_instance<T, WPB, (sizeof(T) == 8), ADAPT>(v, b, (int)gridDim.x - 1, p.error, p.spin_limit);
 }
 
 // Serving: the launch's workgroups are dealt to the resident solves by a work

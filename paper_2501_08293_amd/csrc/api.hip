@@ -143,7 +143,8 @@ struct opf_admm_handle {
     double* devBbar = nullptr;
     int64_t devF_count = 0;
     int lds_cols = 0;              // factor columns of the largest workgroup
-    int lds32 = 0, lds64 = 0;      // factors resident in LDS for each precision
+    int lds32 = 0, lds64 = 0;      // factors in LDS: FP32 all (1) or none; FP64 column budget (0: none)
+    int lds64_cols = 0;            // dynamic LDS columns of the FP64 launch
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double kernel_ms = 0;          // device time of iteration kernels in the current solve
     long long kernel_launches = 0;
@@ -345,7 +346,7 @@ int run_phase_persistent(opf_admm_handle* h, PrecState<T>& s, long long max_iter
     p.spin_limit = h->opt.spin_limit > 0 ? h->opt.spin_limit : 4000000LL;
     p.max_iter = max_iter;
     p.check = check;
-    p.lds_factor_cols = h->lds_cols;
+    p.lds_factor_cols = sizeof(T) == 8 ? h->lds64_cols : h->lds_cols;
     p.lds_factors = sizeof(T) == 8 ? h->lds64 : h->lds32;
     HIPCHK(hipEventRecord(h->ev0, h->stream));
     HIPCHK(launch_persistent<T>(a, p, h->wpb, h->lay.blocks, h->stream));
@@ -916,14 +917,32 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
         h->lds_cols = std::max(h->lds_cols, cols);
     }
     const size_t lds_limit = 64 * 1024;
-    const size_t l64 = (size_t)h->lds_cols * 64 * 8, l32 = (size_t)h->lds_cols * 64 * 4;
+    const size_t l32 = (size_t)h->lds_cols * 64 * 4;
     const int ad = opt.rho_every > 0;
-    const int cap64_lds = l64 <= lds_limit ? persistent_capacity<double>(h->wpb, l64, ad) : 0;
     const int cap32_lds = l32 <= lds_limit ? persistent_capacity<float>(h->wpb, l32, ad) : 0;
-    h->lds64 = cap64_lds >= blocks + 1;
     h->lds32 = cap32_lds >= blocks + 1;
-    const int cap64 = h->lds64 ? cap64_lds : persistent_capacity<double>(h->wpb, 0, ad);
     const int cap32 = h->lds32 ? cap32_lds : persistent_capacity<float>(h->wpb, 0, ad);
+    // FP64: the largest column budget (every workgroup's columns, else a
+    // multiple of 8) with which the grid still fits; workgroups within it
+    // hold their factors in LDS
+    int cap64 = persistent_capacity<double>(h->wpb, 0, ad);
+    h->lds64 = 0;
+    h->lds64_cols = 0;
+    std::vector<int> budgets{h->lds_cols};
+    for (int c = h->lds_cols / 8 * 8; c >= 8; c -= 8)
+        if (c < h->lds_cols) budgets.push_back(c);
+    for (int cols : budgets) {
+        if (cols < 1) break;
+        const size_t l64 = (size_t)cols * 64 * 8;
+        if (l64 > lds_limit) continue;
+        const int c = persistent_capacity<double>(h->wpb, l64, ad);
+        if (c >= blocks + 1) {
+            h->lds64 = cols;
+            h->lds64_cols = cols;
+            cap64 = c;
+            break;
+        }
+    }
     h->capacity = opt.precision == OPF_PREC_MIXED ? std::min(cap32, cap64) : cap64;
     if (opt.kernel == OPF_KERNEL_PERSISTENT && h->capacity < blocks + 1)
         return fail(set_err(h, OPF_EINVAL, "persistent kernel needs " + std::to_string(blocks + 1) +
@@ -1046,7 +1065,16 @@ int opf_admm_get_info(const opf_admm_handle* h, opf_admm_info* info) {
     info->kernel = h->kernel;
     info->persistent_capacity = h->capacity;
     info->max_neighbours = h->lay.max_nbrs;
-    info->factors_in_lds = h->lds32 | (h->lds64 << 1);
+    info->factors_in_lds = (h->lds32 ? 1 : 0) | (h->lds64 ? 2 : 0);
+    if (h->lds64) {
+        int in = 0;
+        for (int b2 = 0; b2 < h->lay.blocks; ++b2) {
+            int cols = 0;
+            for (int q = 0; q < h->wpb; ++q) cols += h->lay.wave_maxn[(size_t)b2 * h->wpb + q];
+            in += cols <= h->lds64;
+        }
+        info->fp64_lds_workgroups = in;
+    }
     if (h->kernel == OPF_KERNEL_TILED)
         info->tiled_pair = h->opt.precision == OPF_PREC_MIXED ? h->tiled_pair32 : h->tiled_pair64;
     return 0;
