@@ -198,6 +198,8 @@ struct TiledArgs {
     int tiles;                  // workgroup tiles of the packing (block_waves wavefronts each)
     int n;
     int pair;                   // 1: at most two tiles per workgroup, both in flight (admm_tiled_pair_kernel)
+    int lds_cols;               // two-tile kernel: factor columns of dynamic shared memory per workgroup; a
+                                // workgroup whose tiles' columns fit keeps their factors there (0: none)
 };
 
 // Iterations between a residual reduction and the moment workgroups act on

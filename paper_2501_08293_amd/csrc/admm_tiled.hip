@@ -272,6 +272,19 @@ __global__ __launch_bounds__(WPB * 64) void admm_tiled_pair_kernel(IterArgs<T> a
     T* xr = static_cast<T*>(ta.xr);
     const T inv_rho = a.inv_rho, rho = a.rho;
     const int ntile = b + G < ta.tiles ? 2 : 1;          // the same for the whole workgroup
+    // factors of this workgroup's wavefronts (tile 0's, then tile 1's) copied
+    // once into LDS when their columns fit the launch's budget; each lane
+    // reads back only what it wrote, so no barrier is needed
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    T* Fl = reinterpret_cast<T*>(dyn_lds);
+    int wg_cols = 0, off_cols[2] = {0, 0};
+    for (int q = 0; q < ntile; ++q)
+        for (int v = 0; v < WPB; ++v) {
+            const int c = a.winfo[(b + q * G) * WPB + v].x;
+            if (v == wv) off_cols[q] = wg_cols;
+            wg_cols += c;
+        }
+    const bool in_lds = ta.lds_cols > 0 && wg_cols <= ta.lds_cols;
     PairSlot<T> S[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -300,6 +313,16 @@ __global__ __launch_bounds__(WPB * 64) void admm_tiled_pair_kernel(IterArgs<T> a
                 u.z = zr[r0 * LP + u.d];
                 u.l = lr[r0 * LP + u.d];
             }
+        }
+    }
+    const T* Fsrc[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        Fsrc[q] = a.F + (size_t)S[q].wi.y * 64;
+        if (in_lds && q < ntile) {
+            T* dst = Fl + (size_t)off_cols[q] * 64;
+            for (int k = 0; k < S[q].wi.x; ++k) dst[k * 64 + lane] = Fsrc[q][k * 64 + lane];
+            Fsrc[q] = dst;
         }
     }
     long long t = t0;
@@ -412,9 +435,8 @@ __global__ __launch_bounds__(WPB * 64) void admm_tiled_pair_kernel(IterArgs<T> a
         }
         __builtin_amdgcn_wave_barrier();
         T zn[2] = {S[0].bb, S[1].bb};
-        project_rows2(a.F + (size_t)S[0].wi.y * 64, vsh[0][wv], S[0].meta & 255, S[0].g >= 0 ? S[0].wi.x : 0, zn[0],
-                      a.F + (size_t)S[1].wi.y * 64, vsh[1][wv], S[1].meta & 255, S[1].g >= 0 ? S[1].wi.x : 0, zn[1],
-                      lane);
+        project_rows2(Fsrc[0], vsh[0][wv], S[0].meta & 255, S[0].g >= 0 ? S[0].wi.x : 0, zn[0],
+                      Fsrc[1], vsh[1][wv], S[1].meta & 255, S[1].g >= 0 ? S[1].wi.x : 0, zn[1], lane);
         double s[5] = {0, 0, 0, 0, 0};
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -490,11 +512,12 @@ hipError_t launch_tiled(const IterArgs<T>& a, PersistArgs p, const TiledArgs& ta
     TiledArgs t = ta;
     void* args[] = {(void*)&a, (void*)&p, (void*)&t};
     if (ta.pair) {
+        const size_t lds = (size_t)ta.lds_cols * 64 * sizeof(T);
         switch (wpb) {
-            case 1: return hipLaunchCooperativeKernel((const void*)admm_tiled_pair_kernel<T, 1>, dim3(G + 1), dim3(64), args, 0, st);
-            case 2: return hipLaunchCooperativeKernel((const void*)admm_tiled_pair_kernel<T, 2>, dim3(G + 1), dim3(128), args, 0, st);
-            case 8: return hipLaunchCooperativeKernel((const void*)admm_tiled_pair_kernel<T, 8>, dim3(G + 1), dim3(512), args, 0, st);
-            default: return hipLaunchCooperativeKernel((const void*)admm_tiled_pair_kernel<T, 4>, dim3(G + 1), dim3(256), args, 0, st);
+            case 1: return hipLaunchCooperativeKernel((const void*)admm_tiled_pair_kernel<T, 1>, dim3(G + 1), dim3(64), args, lds, st);
+            case 2: return hipLaunchCooperativeKernel((const void*)admm_tiled_pair_kernel<T, 2>, dim3(G + 1), dim3(128), args, lds, st);
+            case 8: return hipLaunchCooperativeKernel((const void*)admm_tiled_pair_kernel<T, 8>, dim3(G + 1), dim3(512), args, lds, st);
+            default: return hipLaunchCooperativeKernel((const void*)admm_tiled_pair_kernel<T, 4>, dim3(G + 1), dim3(256), args, lds, st);
         }
     }
     switch (wpb) {
@@ -507,20 +530,20 @@ hipError_t launch_tiled(const IterArgs<T>& a, PersistArgs p, const TiledArgs& ta
 template hipError_t launch_tiled<double>(const IterArgs<double>&, PersistArgs, const TiledArgs&, int, int, hipStream_t);
 template hipError_t launch_tiled<float>(const IterArgs<float>&, PersistArgs, const TiledArgs&, int, int, hipStream_t);
 
-// Co-resident workgroups of the tiled kernel (pair = 1: the two-tile kernel)
-// (0 on error).
+// Co-resident workgroups of the tiled kernel (pair = 1: the two-tile kernel,
+// with lds_bytes of dynamic shared memory per workgroup) (0 on error).
 template <typename T>
-int tiled_capacity(int wpb, int pair) {
+int tiled_capacity(int wpb, int pair, size_t lds_bytes) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e;
     if (pair) {
         switch (wpb) {
-            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 1>, 64, 0); break;
-            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 2>, 128, 0); break;
-            case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 8>, 512, 0); break;
-            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 4>, 256, 0); break;
+            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 1>, 64, lds_bytes); break;
+            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 2>, 128, lds_bytes); break;
+            case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 8>, 512, lds_bytes); break;
+            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 4>, 256, lds_bytes); break;
         }
     } else {
         switch (wpb) {
@@ -533,7 +556,7 @@ int tiled_capacity(int wpb, int pair) {
     if (e != hipSuccess) return 0;
     return per * cus;
 }
-template int tiled_capacity<double>(int, int);
-template int tiled_capacity<float>(int, int);
+template int tiled_capacity<double>(int, int, size_t);
+template int tiled_capacity<float>(int, int, size_t);
 
 }  // namespace opf

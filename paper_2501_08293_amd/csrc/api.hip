@@ -34,7 +34,7 @@ hipError_t launch_persistent(const IterArgs<T>& a, PersistArgs p, int wpb, int G
 template <typename T> int persistent_capacity(int wpb, size_t lds_bytes, int adapt);
 template <typename T>
 hipError_t launch_tiled(const IterArgs<T>& a, PersistArgs p, const TiledArgs& ta, int wpb, int G, hipStream_t st);
-template <typename T> int tiled_capacity(int wpb, int pair);
+template <typename T> int tiled_capacity(int wpb, int pair, size_t lds_bytes = 0);
 template <typename T>
 hipError_t launch_output(const T* z0, const T* z1, const T* l0, const T* l1, const T* x0, const T* x1,
                          const int* user_slot, int LP, int n, const double* c, double* xo, double* zo,
@@ -136,6 +136,7 @@ struct opf_admm_handle {
     int tiled_G = 0;               // tiled schedule: compute workgroups of the FP64 kernel (tiles = lay.blocks)
     int tiled_G32 = 0;             // and of the FP32 kernel
     int tiled_pair64 = 0, tiled_pair32 = 0;   // the two-tile kernel runs (per precision)
+    int tiled_lds64 = 0, tiled_lds32 = 0;     // its factor column budget in LDS (0: factors from memory)
     Work work;                     // the handle's own kernel scratch
     int xcd_remap = 1;
     int* error_host = nullptr;     // pinned
@@ -387,6 +388,7 @@ int run_phase_tiled(opf_admm_handle* h, PrecState<T>& s, long long max_iter, int
     ta.tiles = h->lay.blocks;
     ta.n = h->lay.n;
     ta.pair = sizeof(T) == 4 ? h->tiled_pair32 : h->tiled_pair64;
+    ta.lds_cols = sizeof(T) == 4 ? h->tiled_lds32 : h->tiled_lds64;
     HIPCHK(hipEventRecord(h->ev0, h->stream));
     HIPCHK(launch_tiled<T>(a, p, ta, h->wpb, sizeof(T) == 4 ? h->tiled_G32 : h->tiled_G, h->stream));
     HIPCHK(hipEventRecord(h->ev1, h->stream));
@@ -975,6 +977,30 @@ int opf_admm_setup(const opf_problem* p, const opf_admm_options* o, void* hip_st
     if (tiled_ok) {
         h->tiled_G = tiled_grid(tcap64, pcap64, &h->tiled_pair64);
         h->tiled_G32 = tiled_grid(tcap32, pcap32, &h->tiled_pair32);
+        // two-tile kernel: the largest column budget of dynamic shared memory
+        // (every workgroup's two tiles, else a multiple of 8) with which its
+        // grid still fits; workgroups within it keep their factors in LDS
+        auto pair_budget = [&](int G, size_t elem, bool fp32) {
+            int most = 0;
+            for (int b2 = 0; b2 < G; ++b2) {
+                int cols = 0;
+                for (int q = 0; q < 2 && b2 + q * G < blocks; ++q)
+                    for (int v = 0; v < h->wpb; ++v) cols += L.wave_maxn[(size_t)(b2 + q * G) * h->wpb + v];
+                most = std::max(most, cols);
+            }
+            std::vector<int> budgets{most};
+            for (int c = most / 8 * 8; c >= 8; c -= 8)
+                if (c < most) budgets.push_back(c);
+            for (int cols : budgets) {
+                const size_t bytes = (size_t)cols * 64 * elem;
+                if (cols < 1 || bytes > lds_limit) continue;
+                const int cap = fp32 ? tiled_capacity<float>(h->wpb, 1, bytes) : tiled_capacity<double>(h->wpb, 1, bytes);
+                if (cap >= G + 1) return cols;
+            }
+            return 0;
+        };
+        if (h->tiled_pair64) h->tiled_lds64 = pair_budget(h->tiled_G, 8, false);
+        if (h->tiled_pair32) h->tiled_lds32 = pair_budget(h->tiled_G32, 4, true);
     }
     if (opt.kernel == OPF_KERNEL_TILED && !tiled_ok)
         return fail(set_err(h, OPF_EINVAL, "the tiled schedule runs a fixed penalty on a device holding at least "
