@@ -53,23 +53,26 @@ __device__ __forceinline__ T project_row(const T* F, const T* v, int base, int l
 // DPP lane moves (no LDS traffic): an inclusive scan inside each row of 16
 // lanes (shifts 1, 2, 4, 8), then row 0 into row 1 and row 2 into row 3, then
 // rows 0-1 into rows 2-3; lane 63 ends with the total, which every lane
-// receives.  Used by every schedule, so all reduce in the same order.
+// receives.  Used by every schedule, so all reduce in the same order.  Lanes
+// without a source lane read 0 (bound_ctrl), so no move needs a zeroed
+// destination; the broadcasts also add into rows whose sums lane 63 never
+// reads again (row 2 at the first, rows 0 and 1 at the second).
 __device__ __forceinline__ double dpp_move(double v, int ctrl_id) {
     const long long b = __double_as_longlong(v);
     int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
     switch (ctrl_id) {
-        case 0: lo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xf, 0xf, false);
-                hi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, false); break;   // row_shr:1
-        case 1: lo = __builtin_amdgcn_update_dpp(0, lo, 0x112, 0xf, 0xf, false);
-                hi = __builtin_amdgcn_update_dpp(0, hi, 0x112, 0xf, 0xf, false); break;   // row_shr:2
-        case 2: lo = __builtin_amdgcn_update_dpp(0, lo, 0x114, 0xf, 0xf, false);
-                hi = __builtin_amdgcn_update_dpp(0, hi, 0x114, 0xf, 0xf, false); break;   // row_shr:4
-        case 3: lo = __builtin_amdgcn_update_dpp(0, lo, 0x118, 0xf, 0xf, false);
-                hi = __builtin_amdgcn_update_dpp(0, hi, 0x118, 0xf, 0xf, false); break;   // row_shr:8
-        case 4: lo = __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xa, 0xf, false);
-                hi = __builtin_amdgcn_update_dpp(0, hi, 0x142, 0xa, 0xf, false); break;   // row_bcast:15
-        default: lo = __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xc, 0xf, false);
-                 hi = __builtin_amdgcn_update_dpp(0, hi, 0x143, 0xc, 0xf, false); break;  // row_bcast:31
+        case 0: lo = __builtin_amdgcn_mov_dpp(lo, 0x111, 0xf, 0xf, true);
+                hi = __builtin_amdgcn_mov_dpp(hi, 0x111, 0xf, 0xf, true); break;   // row_shr:1
+        case 1: lo = __builtin_amdgcn_mov_dpp(lo, 0x112, 0xf, 0xf, true);
+                hi = __builtin_amdgcn_mov_dpp(hi, 0x112, 0xf, 0xf, true); break;   // row_shr:2
+        case 2: lo = __builtin_amdgcn_mov_dpp(lo, 0x114, 0xf, 0xf, true);
+                hi = __builtin_amdgcn_mov_dpp(hi, 0x114, 0xf, 0xf, true); break;   // row_shr:4
+        case 3: lo = __builtin_amdgcn_mov_dpp(lo, 0x118, 0xf, 0xf, true);
+                hi = __builtin_amdgcn_mov_dpp(hi, 0x118, 0xf, 0xf, true); break;   // row_shr:8
+        case 4: lo = __builtin_amdgcn_mov_dpp(lo, 0x142, 0xf, 0xf, true);
+                hi = __builtin_amdgcn_mov_dpp(hi, 0x142, 0xf, 0xf, true); break;   // row_bcast:15
+        default: lo = __builtin_amdgcn_mov_dpp(lo, 0x143, 0xf, 0xf, true);
+                 hi = __builtin_amdgcn_mov_dpp(hi, 0x143, 0xf, 0xf, true); break;  // row_bcast:31
     }
     return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
 }
