@@ -129,6 +129,33 @@ __host__ __device__ __forceinline__ double rho_decide(const RhoRule& r, double p
     return v < r.lo ? r.lo : (v > r.hi ? r.hi : v);
 }
 
+// Workgroups of kernel `fn` that one compute unit holds at once with `dyn`
+// bytes of dynamic shared memory: the occupancy query, further bounded by
+// counting each workgroup's LDS (static and dynamic) in whole 4 KiB blocks.
+// The query counts bytes: a grid it admitted at three workgroups per compute
+// unit, 2.3 KiB short of the LDS, was not co-resident on gfx950, while grids
+// whose workgroups fit the LDS in whole 4 KiB blocks have been (a persistent
+// grid that is not co-resident can only end by its bounded waits).  The
+// bound applies only where the device's LDS size agrees with the query.
+constexpr size_t kLdsBlock = 4096;
+inline hipError_t resident_per_cu(int* per, const void* fn, int threads, size_t dyn) {
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, fn, threads, dyn);
+    if (e != hipSuccess) return e;
+    hipFuncAttributes at;
+    int dev = 0, lds = 0;
+    if ((e = hipFuncGetAttributes(&at, fn)) != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev)) != hipSuccess)
+        return e;
+    const size_t bytes = at.sharedSizeBytes + dyn;
+    const size_t need = (bytes + kLdsBlock - 1) / kLdsBlock * kLdsBlock;
+    if (bytes > 0 && *per > 0 && (size_t)lds >= (size_t)*per * bytes) {
+        const int fit = (int)((size_t)lds / need);
+        if (fit < *per) *per = fit;
+    }
+    return hipSuccess;
+}
+
 // Control block in device memory; written by the last workgroup of each
 // iteration, read by the host between launches and by the next iteration.
 struct Ctrl {

@@ -406,7 +406,7 @@ int serve_capacity(size_t lds_bytes, int fp32) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     const void* k = fp32 ? (const void*)admm_serve_kernel<float> : (const void*)admm_serve_kernel<double>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kServeWPB * 64, lds_bytes) != hipSuccess) return 0;
+    if (resident_per_cu(&per, k, kServeWPB * 64, lds_bytes) != hipSuccess) return 0;
     return per * cus;
 }
 
@@ -483,10 +483,10 @@ int persistent_capacity_as(int wpb, size_t lds_bytes) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e;
     switch (wpb) {
-        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 1, ADAPT>, 64, lds_bytes); break;
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 2, ADAPT>, 128, lds_bytes); break;
-        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 8, ADAPT>, 512, lds_bytes); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_persistent_kernel<T, 4, ADAPT>, 256, lds_bytes); break;
+        case 1: e = resident_per_cu(&per, (const void*)admm_persistent_kernel<T, 1, ADAPT>, 64, lds_bytes); break;
+        case 2: e = resident_per_cu(&per, (const void*)admm_persistent_kernel<T, 2, ADAPT>, 128, lds_bytes); break;
+        case 8: e = resident_per_cu(&per, (const void*)admm_persistent_kernel<T, 8, ADAPT>, 512, lds_bytes); break;
+        default: e = resident_per_cu(&per, (const void*)admm_persistent_kernel<T, 4, ADAPT>, 256, lds_bytes); break;
     }
     if (e != hipSuccess) return 0;
     return per * cus;

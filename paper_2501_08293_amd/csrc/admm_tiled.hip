@@ -540,17 +540,17 @@ int tiled_capacity(int wpb, int pair, size_t lds_bytes) {
     hipError_t e;
     if (pair) {
         switch (wpb) {
-            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 1>, 64, lds_bytes); break;
-            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 2>, 128, lds_bytes); break;
-            case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 8>, 512, lds_bytes); break;
-            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_pair_kernel<T, 4>, 256, lds_bytes); break;
+            case 1: e = resident_per_cu(&per, (const void*)admm_tiled_pair_kernel<T, 1>, 64, lds_bytes); break;
+            case 2: e = resident_per_cu(&per, (const void*)admm_tiled_pair_kernel<T, 2>, 128, lds_bytes); break;
+            case 8: e = resident_per_cu(&per, (const void*)admm_tiled_pair_kernel<T, 8>, 512, lds_bytes); break;
+            default: e = resident_per_cu(&per, (const void*)admm_tiled_pair_kernel<T, 4>, 256, lds_bytes); break;
         }
     } else {
         switch (wpb) {
-            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_kernel<T, 1>, 64, 0); break;
-            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_kernel<T, 2>, 128, 0); break;
-            case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_kernel<T, 8>, 512, 0); break;
-            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, admm_tiled_kernel<T, 4>, 256, 0); break;
+            case 1: e = resident_per_cu(&per, (const void*)admm_tiled_kernel<T, 1>, 64, 0); break;
+            case 2: e = resident_per_cu(&per, (const void*)admm_tiled_kernel<T, 2>, 128, 0); break;
+            case 8: e = resident_per_cu(&per, (const void*)admm_tiled_kernel<T, 8>, 512, 0); break;
+            default: e = resident_per_cu(&per, (const void*)admm_tiled_kernel<T, 4>, 256, 0); break;
         }
     }
     if (e != hipSuccess) return 0;
