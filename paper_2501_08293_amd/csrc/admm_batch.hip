@@ -80,8 +80,11 @@ __device__ __forceinline__ double wave_sum_b(double v) {
 // Phases 1 and 3 share one layout (wave wv: slots 16 wv .. 16 wv + 15, lane:
 // scenario), so x and the slot's own lambda, loaded in phase 1, stay in
 // registers until phase 3; the product Z comes back from the matrix cores
-// through the V tile's LDS.  LDS 30 KiB.
-__global__ __launch_bounds__(256) void admm_batch_step_kernel(BatchArgs a) {
+// through the V tile's LDS.  LDS 30 KiB.  Four wavefronts per SIMD (at most
+// 128 registers; the matrix-core accumulators live in ordinary VGPRs): the
+// kernel is bound by the latency of its dependent memory rounds, so the
+// fourth workgroup per CU is worth more than a few registers.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void admm_batch_step_kernel(BatchArgs a) {
     if (a.ctrl->stop) return;
     const long long t = a.ctrl->iter + 1;
     const bool odd = (t & 1) != 0;
