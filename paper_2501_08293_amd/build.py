@@ -23,11 +23,24 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def compile_flags() -> list:
+    """hipcc flags of every translation unit (device code for ARCH only)."""
+    return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I", os.path.join(ROOT, "include")]
+
+
+def device_assembly(src: str, out: str) -> str:
+    """gfx950 assembly of one HIP source of csrc/ (with the compiler's
+    per-kernel resource comments: registers, occupancy, scratch)."""
+    cmd = [hipcc()] + compile_flags() + ["-x", "hip", "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", out]
+    subprocess.run(cmd, check=True, stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    return out
+
+
 def build(verbose: bool = False) -> str:
     objs = []
-    common = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
-              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-I", os.path.join(ROOT, "include")]
+    common = compile_flags()
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
