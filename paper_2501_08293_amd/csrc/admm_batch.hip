@@ -196,17 +196,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void a
     const int vw = a.wave_var ? a.wave_var[w] : -1;
     if (vw >= 0) {
         // per-scenario factors: output (row r, scenario col) of this lane's
-        // sixteen tile positions, summed over the component's columns in order
+        // sixteen tile positions, each summed over the component's columns in
+        // order; the sixteen factor loads of one column are in flight together
         const int col = 32 * nt + l32;
-        const size_t kk = (size_t)(kc + col);
+        const int r0 = 32 * m + 4 * grp;     // row of tile position v: r0 + 8 (v / 4) + v % 4
+        // column base lanes of the sixteen rows (< 64), four to a register
+        unsigned bases[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int r = 32 * m + 8 * (v >> 2) + 4 * grp + (v & 3);
-            const int base = a.meta[(size_t)w * 64 + r] & 255;
-            const float* Fr = a.Fv + ((size_t)vw * a.fv_cols * 64 + r) * Kp + kk;
-            float z = 0.0f;
-            for (int j = 0; j < a.fv_cols; ++j) z = fmadd(Fr[(size_t)j * 64 * Kp], vs[(base + j) & 63][col], z);
-            acc[v] = z;
+        for (int v = 0; v < 16; ++v)
+            bases[v >> 2] |= (unsigned)(a.meta[(size_t)w * 64 + r0 + 8 * (v >> 2) + (v & 3)] & 255) << (8 * (v & 3));
+        // this wavefront's factors [column][row][scenario] from one base, at 32-bit
+        // byte offsets (at most 64 x 64 x 4096 floats)
+        const float* Fw = a.Fv + (size_t)vw * a.fv_cols * 64 * Kp;
+        const uint32_t rs = (uint32_t)Kp * 4u, js = 64u * rs;
+        const uint32_t o0 = (uint32_t)r0 * rs + (uint32_t)(kc + col) * 4u;
+        for (int j = 0; j < a.fv_cols; ++j) {
+            const uint32_t oj = o0 + (uint32_t)j * js;
+            float f[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) f[v] = ld32(Fw, oj + (uint32_t)(8 * (v >> 2) + (v & 3)) * rs);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int bv = (int)((bases[v >> 2] >> (8 * (v & 3))) & 255u);
+                acc[v] = fmadd(f[v], vs[(bv + j) & 63][col], acc[v]);
+            }
         }
     } else {
     const size_t plane = (size_t)a.W * 64 * 64;
