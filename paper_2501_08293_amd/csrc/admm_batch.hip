@@ -141,41 +141,58 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void a
     __syncthreads();
 
     // ---- phase 1: consensus average and projection input, 16 slots per
-    // wave in groups of four whose gathers are in flight together
+    // wave in groups of eight: copies 0 and 1 of the eight slots are gathered
+    // together, then copies 2-3 and 4-5 only where some of the eight slots
+    // have them (a slot's copy count is the same on every lane); each slot's
+    // terms are summed in copy order
     const uint32_t lane4 = 4u * lane;
     float xr[16], lr[16];
 #pragma unroll
-    for (int r0 = 0; r0 < 16; r0 += 4) {
-        float zz[4][kBatchCopies], ll[4][kBatchCopies];
+    for (int r0 = 0; r0 < 16; r0 += 8) {
+        float acc[8];
+        int cmax = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = wv * 16 + r0 + j;
-            const int cn = s_cn[r];
-            const uint32_t dk = (uint32_t)(w * 64 + r) * 256u + lane4;
+        for (int q0 = 0; q0 < kBatchCopies; q0 += 2) {
+            if (q0 > 0 && q0 >= cmax) break;
+            float zz[8][2], ll[8][2];
 #pragma unroll
-            for (int q = 0; q < kBatchCopies; ++q) {
-                const uint32_t e = (uint32_t)s_copy[r][q] * 256u + lane4;
-                zz[j][q] = q < cn ? ld32(zp, e) : 0.0f;
-                ll[j][q] = q < cn ? ld32(lp, e) : 0.0f;
+            for (int j = 0; j < 8; ++j) {
+                const int r = wv * 16 + r0 + j;
+                const int cn = s_cn[r];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const uint32_t e = (uint32_t)s_copy[r][q0 + q] * 256u + lane4;
+                    zz[j][q] = q0 + q < cn ? ld32(zp, e) : 0.0f;
+                    ll[j][q] = q0 + q < cn ? ld32(lp, e) : 0.0f;
+                }
+                if (q0 == 0) {
+                    const uint32_t dk = (uint32_t)(w * 64 + r) * 256u + lane4;
+                    lr[r0 + j] = s_var[r] >= 0 ? ld32(lp, dk) : 0.0f;
+                    cmax = cn > cmax ? cn : cmax;
+                }
             }
-            lr[r0 + j] = s_var[r] >= 0 ? ld32(lp, dk) : 0.0f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int cn = s_cn[wv * 16 + r0 + j];
+                if (q0 == 0) acc[j] = 0.0f;
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (q0 + q < cn) acc[j] += zz[j][q] - ll[j][q] * a.inv_rho;
+            }
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 8; ++j) {
             const int r = wv * 16 + r0 + j;
             const int g = s_var[r];
             const int cn = s_cn[r];
             float xv = 0.0f, vv = 0.0f;
             if (g >= 0) {
-                float acc = 0.0f;
-#pragma unroll
-                for (int q = 0; q < kBatchCopies; ++q)
-                    if (q < cn) acc += zz[j][q] - ll[j][q] * a.inv_rho;
+                float sum = acc[j];
                 for (int q = kBatchCopies; q < cn; ++q) {
                     const uint32_t e = (uint32_t)a.clist[s_cs[r] + q] * 256u + lane4;
-                    acc += ld32(zp, e) - ld32(lp, e) * a.inv_rho;
+                    sum += ld32(zp, e) - ld32(lp, e) * a.inv_rho;
                 }
-                const float xh = (acc - s_cost[r]) / (float)cn;
+                const float xh = (sum - s_cost[r]) / (float)cn;
                 xv = xh < s_lo[r] ? s_lo[r] : (xh > s_hi[r] ? s_hi[r] : xh);
                 vv = xv + lr[r0 + j] * a.inv_rho;
                 if (s_owner[r]) st32(xq, (uint32_t)g * 256u + lane4, xv);
