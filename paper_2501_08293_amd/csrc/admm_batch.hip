@@ -287,15 +287,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void a
     for (int v = 0; v < 16; ++v) vs[32 * m + 8 * (v >> 2) + 4 * grp + (v & 3)][32 * nt + l32] = acc[v];
     __syncthreads();
 
-    // ---- phase 3: z = Z + bbar, dual update, residual partials (phase 1's layout)
+    // ---- phase 3: z = Z + bbar, dual update, residual partials (phase 1's layout).
+    // The old z and bbar of all sixteen slots are loaded before any store (a
+    // load after a store to a possibly aliasing address would wait for it),
+    // unconditionally: padding slots have state too, and a conditional load
+    // would wait at its branch's join.
+    float zo16[16], bb16[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t dk = (uint32_t)(w * 64 + wv * 16 + j) * 256u + lane4;
+        zo16[j] = ld32(zp, dk);
+        bb16[j] = ld32(bbar, dk);
+    }
     double s[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int r = wv * 16 + j;
         if (s_var[r] >= 0) {
             const uint32_t dk = (uint32_t)(w * 64 + r) * 256u + lane4;
-            const float zo = ld32(zp, dk);
-            const float zn = vs[r][lane] + ld32(bbar, dk);
+            const float zo = zo16[j];
+            const float zn = vs[r][lane] + bb16[j];
             const float xv = xr[j];
             const float ln = lr[j] + a.rho * (xv - zn);
             st32(zq, dk, zn);
