@@ -7,7 +7,7 @@
 
 namespace opf {
 
-constexpr int kBatchKernelRev = 7;   // revision of the step kernel (tuning decisions are kept per revision)
+constexpr int kBatchKernelRev = 8;   // revision of the step kernel (tuning decisions are kept per revision)
 constexpr int kBatchCopies = 6;    // copies per variable gathered from the slot record (more: from the copy list)
 
 // ---- batched same-topology scenarios (see admm_batch.hip)

@@ -217,17 +217,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void a
         // order; the sixteen factor loads of one column are in flight together
         const int col = 32 * nt + l32;
         const int r0 = 32 * m + 4 * grp;     // row of tile position v: r0 + 8 (v / 4) + v % 4
-        // column base lanes of the sixteen rows (< 64), four to a register
+        // column base lanes of the sixteen rows (< 64), four to a register, and
+        // the largest component size among the wavefront's rows: the factors of
+        // a row are zero past its component's columns, so the columns beyond
+        // every row's size are skipped
         unsigned bases[4] = {0u, 0u, 0u, 0u};
+        int ncol = 0;
 #pragma unroll
-        for (int v = 0; v < 16; ++v)
-            bases[v >> 2] |= (unsigned)(a.meta[(size_t)w * 64 + r0 + 8 * (v >> 2) + (v & 3)] & 255) << (8 * (v & 3));
+        for (int v = 0; v < 16; ++v) {
+            const int mt = a.meta[(size_t)w * 64 + r0 + 8 * (v >> 2) + (v & 3)];
+            bases[v >> 2] |= (unsigned)(mt & 255) << (8 * (v & 3));
+            ncol = max(ncol, (mt >> 8) & 255);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ncol = max(ncol, __shfl_xor(ncol, o, 64));
+        ncol = min(__builtin_amdgcn_readfirstlane(ncol), a.fv_cols);
         // this wavefront's factors [column][row][scenario] from one base, at 32-bit
         // byte offsets (at most 64 x 64 x 4096 floats)
         const float* Fw = a.Fv + (size_t)vw * a.fv_cols * 64 * Kp;
         const uint32_t rs = (uint32_t)Kp * 4u, js = 64u * rs;
         const uint32_t o0 = (uint32_t)r0 * rs + (uint32_t)(kc + col) * 4u;
-        for (int j = 0; j < a.fv_cols; ++j) {
+        for (int j = 0; j < ncol; ++j) {
             const uint32_t oj = o0 + (uint32_t)j * js;
             float f[16];
 #pragma unroll
